@@ -1,0 +1,185 @@
+/*
+ * fsim.h -- C ABI of libfsim.so: the direct-SCF restricted Hartree-Fock Fock
+ * build (McMurchie-Davidson electron-repulsion integrals over Schwarz-screened
+ * shell quartets, digested on the fly into J and K) for AMD MI355X (gfx950).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  - Every function returns fsim_status: FSIM_OK (0) or a negative error.
+ *    fsim_last_error() returns a thread-local message for the last error.
+ *    No C++ exception crosses this boundary.
+ *  - "device" pointers are HIP device memory owned by the caller (the library
+ *    never frees them); "host" pointers are ordinary memory, read during the
+ *    call and not retained.
+ *  - Matrices are N x N FP64, row-major, N = number of Cartesian basis
+ *    functions.  Basis functions are ordered shell by shell in input order;
+ *    within a shell the Cartesian components run lx descending, then ly
+ *    descending (p: x, y, z; d: xx, xy, xz, yy, yz, zz).  Each primitive is
+ *    normalised to unit self-overlap and each contracted Cartesian function
+ *    is rescaled to unit self-overlap, so diag(S) = 1.
+ *  - `stream` is a hipStream_t passed as void* (NULL = the null stream).  All
+ *    device work is ordered on it; calls that return host values (energies,
+ *    statistics, SCF info) synchronise the stream before returning.
+ *  - A context is not thread-safe: calls on one context must not overlap.
+ */
+#ifndef FSIM_H
+#define FSIM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    FSIM_OK = 0,
+    FSIM_EINVAL = -1, /* invalid argument: message names it */
+    FSIM_ENOMEM = -2, /* device or host allocation failed */
+    FSIM_EHIP = -3,   /* a HIP, rocBLAS or rocSOLVER call failed */
+    FSIM_ESTATE = -4  /* call out of order (e.g. SCF step before a screen) */
+} fsim_status;
+
+typedef enum {
+    FSIM_FP64 = 0, /* every integral in FP64 */
+    FSIM_MIXED = 1 /* quartets with Schwarz bound below tau_fp32 in FP32,
+                      the rest in FP64; J/K accumulate in FP64 */
+} fsim_precision;
+
+/* Molecule and contracted Cartesian basis (Sec. 2.1: contracted shells of
+ * primitive Cartesian Gaussians sharing a centre and an exponent set).
+ * All host pointers; copied by fsim_ctx_create. */
+typedef struct {
+    int32_t natom;
+    const double *xyz;          /* [natom*3] nuclear positions, bohr */
+    const double *Z;            /* [natom] nuclear charges */
+    int32_t nshell;
+    const int32_t *shell_atom;  /* [nshell] centre of each shell */
+    const int32_t *shell_l;     /* [nshell] 0, 1 or 2 (Cartesian d) */
+    const int32_t *shell_nprim; /* [nshell] 1..8 primitives */
+    const int32_t *shell_prim0; /* [nshell] offset into exps / coefs */
+    const double *exps;         /* primitive exponents, > 0 */
+    const double *coefs;        /* raw contraction coefficients d_k */
+    int32_t nelec;              /* even, 2 <= nelec <= 2N (closed shell) */
+} fsim_basis;
+
+typedef struct {
+    double tau_screen;  /* Schwarz threshold: quartet kept iff Q_ab Q_cd >= tau */
+    double tau_fp32;    /* mixed precision: FP32 iff Q_ab Q_cd < tau_fp32 */
+    int32_t diis_m;     /* DIIS subspace size (1..16); 0 disables DIIS */
+    double conv_rms_dD; /* converged when RMS(D_new - D) < conv_rms_dD ... */
+    double conv_dE;     /* ... and |dE| < conv_dE (ignored if <= 0) */
+    int32_t max_iter;   /* informational: fsim_scf_step never loops */
+} fsim_options;
+
+typedef struct fsim_ctx fsim_ctx;
+
+typedef struct {
+    int64_t shell_pairs;       /* a >= b */
+    int64_t pairs_kept;        /* Q_ab * Q_max >= tau */
+    int64_t quartets_total;    /* canonical shell quartets */
+    int64_t quartets_kept;     /* Schwarz survivors */
+    int64_t quartets_fp64;     /* of which evaluated in FP64 (mixed mode) */
+    int64_t quartets_fp32;     /* of which evaluated in FP32 (mixed mode) */
+    int64_t prim_quartets_kept;
+    double flops_fp64;         /* algorithmic flop model of one FP64-mode build */
+    double flops_mixed_fp64;   /* same, mixed mode, FP64 part */
+    double flops_mixed_fp32;   /* same, mixed mode, FP32 part */
+} fsim_screen_stats;
+
+typedef struct {
+    double E_total;   /* E_elec + E_nuc of the density passed in */
+    double E_elec;    /* 1/2 Tr[D (H + F(D))] */
+    double dE;        /* E_total minus the previous step's (0 on the first) */
+    double rms_dD;    /* ||D_new - D||_F / N */
+    double comm_norm; /* ||F D S - S D F||_F */
+    int32_t iter;     /* steps taken since create / reset */
+    int32_t converged;
+    int32_t diis_used;  /* 1 when the DIIS extrapolation was applied */
+    int32_t pad;
+} fsim_scf_info;
+
+/* Message of the last failed call on this thread ("" if none). */
+const char *fsim_last_error(void);
+
+/* Library version string. */
+const char *fsim_version(void);
+
+/* Build a context on the current HIP device: normalise the basis, build the
+ * shell-pair tables (Sec. 2.4: product centres, exponents and the Hermite
+ * tensors E^{ab}_{tuv} of Eq. E-tuv), the Boys-function tables, the
+ * one-electron matrices S, T + V (Eqs. s-overall, Tab-final, Vab-final), the
+ * symmetric orthogonaliser X = U s^-1/2 U^T, and E_nuc.  Runs on the null
+ * stream and synchronises.  Errors: FSIM_EINVAL for l > 2, nprim outside
+ * 1..8, exps <= 0, non-finite input, odd or out-of-range nelec, NULL
+ * pointers, or an overlap matrix with an eigenvalue below 1e-10. */
+fsim_status fsim_ctx_create(const fsim_basis *basis, const fsim_options *opt, fsim_ctx **out);
+
+/* Free every device and host resource of the context.  NULL is accepted. */
+fsim_status fsim_ctx_destroy(fsim_ctx *ctx);
+
+/* Number of Cartesian basis functions N, and the shell count. */
+fsim_status fsim_nbf(const fsim_ctx *ctx, int32_t *nbf, int32_t *nshell);
+
+/* Nuclear repulsion sum_{A<B} Z_A Z_B / R_AB (host out). */
+fsim_status fsim_nuclear_repulsion(const fsim_ctx *ctx, double *enuc);
+
+/* Copy the one-electron matrices into caller device buffers (any may be
+ * NULL): S, Hcore = T + V, X = U s^-1/2 U^T.  Each N x N. */
+fsim_status fsim_one_electron(fsim_ctx *ctx, double *S, double *H, double *X, void *stream);
+
+/* Schwarz screening.  Q_ab = sqrt(max over components (ab|ab)) for every
+ * shell pair, from diagonal integrals evaluated by the same kernels as the
+ * Fock build.  Pairs with Q_ab * Q_max < tau are dropped; the rest are sorted
+ * by Q in each angular-momentum pair class and rebuilt; the quartet work
+ * lists are then formed per quartet class (canonical (ab|cd), kept iff
+ * Q_ab Q_cd >= tau; in mixed mode FP32 iff Q_ab Q_cd < tau_fp32).  Must be
+ * called before fsim_fock_build; calling it again replaces the lists.
+ * Q_out: device [nshell*nshell] (symmetric) or NULL.  stats: host or NULL.
+ * Screening is not in the paper (it names it as future work, Sec. 5); the
+ * bound is the Cauchy-Schwarz inequality of the ERI inner product. */
+fsim_status fsim_schwarz_screen(fsim_ctx *ctx, double tau, double tau_fp32, double *Q_out,
+                                fsim_screen_stats *stats);
+
+/* Direct Fock build (Eq. fock): from the density D (device, N x N, symmetric)
+ * form J_mn = sum_ls (mn|ls) D_ls, K_mn = sum_ls (ml|ns) D_ls and
+ * F = Hcore + J - K/2, evaluating every kept canonical quartet once and
+ * digesting it into J and K with its permutational-degeneracy factor.
+ * F, J, K: device N x N or NULL.  E_elec: host or NULL; when given, the
+ * stream is synchronised and E_elec = 1/2 Tr[D (Hcore + F)].
+ * FSIM_ESTATE if no screen was run. */
+fsim_status fsim_fock_build(fsim_ctx *ctx, const double *D, double *F, double *J, double *K,
+                            double *E_elec, fsim_precision prec, void *stream);
+
+/* Core-Hamiltonian guess (Sec. 3.2, step 1): diagonalise X^T Hcore X and
+ * write D = 2 C_occ C_occ^T into D (device N x N). */
+fsim_status fsim_core_guess(fsim_ctx *ctx, double *D, void *stream);
+
+/* One SCF iteration (Sec. 3.2, with DIIS of Sec. 3.2.1) on the density D
+ * (device, N x N, overwritten): F = F(D); E = 1/2 Tr[D(H+F)];
+ * e = F D S - S D F joins the DIIS history (size diis_m); from two stored
+ * pairs on, F is replaced by sum c_i F_i with the c_i of the bordered DIIS
+ * system (falling back to F when that system is singular);
+ * F' = X^T F X is diagonalised (rocSOLVER dsyevd) and D <- 2 C_occ C_occ^T
+ * with C = X C'.  info (host, required) reports E, dE, RMS(dD), ||e|| and
+ * convergence (see fsim_options).  Synchronises the stream. */
+fsim_status fsim_scf_step(fsim_ctx *ctx, double *D, fsim_scf_info *info, fsim_precision prec,
+                          void *stream);
+
+/* Forget the DIIS history and the step counter. */
+fsim_status fsim_scf_reset(fsim_ctx *ctx);
+
+/* Contracted ERI blocks (Eq. twoe-final summed over primitives) for n shell
+ * quartets, evaluated by the Fock-build kernels but written out instead of
+ * digested.  quartets: host [n*4] shell indices (a, b, c, d) in any order.
+ * offsets: host [n] element offsets into out; block q is written as
+ * out[offsets[q] + ((i*nb + j)*nc + k)*nd + l] over Cartesian components.
+ * out: device FP64.  Unscreened; works before or after a screen. */
+fsim_status fsim_eri_quartets(fsim_ctx *ctx, int64_t n, const int32_t *quartets,
+                              const int64_t *offsets, double *out, fsim_precision prec,
+                              void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FSIM_H */

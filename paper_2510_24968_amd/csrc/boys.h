@@ -1,0 +1,82 @@
+// Boys function F_n(T) = int_0^1 exp(-T t^2) t^(2n) dt on the device
+// (definition in Sec. 2.3.3; the paper gives no evaluation method).
+//
+// Grid T_k = k * BOYS_DT, k < BOYS_NT.  A class kernel of total angular
+// momentum L stages the orders L .. L+7 of the FP64 grid into LDS, each
+// pre-divided by j!, so that
+//     F_L(T) = sum_j F_{L+j}(T_k) (T_k - T)^j / j!       (dF_n/dT = -F_{n+1})
+// is one 8-term Horner polynomial in (T_k - T) about the nearest grid point,
+// and the lower orders follow from the downward recursion
+//     F_{n-1} = (2 T F_n + exp(-T)) / (2n - 1).
+// For T >= BOYS_TMAX, F_0 = sqrt(pi / T) / 2 (erfc(sqrt T) < 1e-16 there)
+// and the upward recursion F_{n+1} = ((2n + 1) F_n - exp(-T)) / (2T), which
+// is stable for 2T > 2n + 1.  Everything here is FP64.
+#pragma once
+
+#include "fsim_internal.h"
+
+namespace fsim {
+
+__host__ __device__ constexpr double inv_factorial(int j) {
+    double f = 1.0;
+    for (int k = 2; k <= j; ++k) f *= k;
+    return 1.0 / f;
+}
+
+// LDS footprint of one staged table, in doubles.
+constexpr int BOYS_LDS = BOYS_NT * BOYS_NTAYLOR;
+
+__device__ inline void boys_stage(double *lds, const double *__restrict__ g, int L) {
+    for (int i = threadIdx.x; i < BOYS_LDS; i += blockDim.x) {
+        int k = i / BOYS_NTAYLOR, j = i - k * BOYS_NTAYLOR;
+        double s = 1.0;
+        for (int m = 2; m <= j; ++m) s *= m;
+        lds[i] = g[k * BOYS_NORD + L + j] / s;
+    }
+}
+
+// F_0..F_L at T from a table staged for order L.
+template <int L>
+__device__ __forceinline__ void boys_eval(double T, const double *tab, double *F) {
+    if (T < BOYS_TMAX) {
+        const int k = __double2int_rn(T * BOYS_INV_DT);
+        const double d = k * BOYS_DT - T;
+        const double *c = tab + k * BOYS_NTAYLOR;
+        double f = c[BOYS_NTAYLOR - 1];
+#pragma unroll
+        for (int j = BOYS_NTAYLOR - 2; j >= 0; --j) f = fma(f, d, c[j]);
+        F[L] = f;
+        if constexpr (L > 0) {
+            const double e = exp(-T), t2 = 2.0 * T;
+#pragma unroll
+            for (int n = L; n > 0; --n) F[n - 1] = fma(t2, F[n], e) * (1.0 / (2 * n - 1));
+        }
+    } else {
+        F[0] = 0.88622692545275801365 * rsqrt(T);   // sqrt(pi)/2 / sqrt(T)
+        if constexpr (L > 0) {
+            const double e = exp(-T), h = 0.5 / T;
+#pragma unroll
+            for (int n = 0; n < L; ++n) F[n + 1] = ((2 * n + 1) * F[n] - e) * h;
+        }
+    }
+}
+
+// Runtime-L variant reading the full global grid (setup kernels only).
+__device__ inline void boys_eval_rt(int L, double T, const double *__restrict__ g, double *F) {
+    if (T < BOYS_TMAX) {
+        const int k = __double2int_rn(T * BOYS_INV_DT);
+        const double d = k * BOYS_DT - T;
+        double f = 0.0;
+        for (int j = BOYS_NTAYLOR - 1; j >= 0; --j)
+            f = fma(f, d, g[k * BOYS_NORD + L + j] * inv_factorial(j));
+        F[L] = f;
+        const double e = exp(-T), t2 = 2.0 * T;
+        for (int n = L; n > 0; --n) F[n - 1] = (t2 * F[n] + e) / (2 * n - 1);
+    } else {
+        F[0] = 0.88622692545275801365 * rsqrt(T);
+        const double e = exp(-T), h = 0.5 / T;
+        for (int n = 0; n < L; ++n) F[n + 1] = ((2 * n + 1) * F[n] - e) * h;
+    }
+}
+
+}  // namespace fsim

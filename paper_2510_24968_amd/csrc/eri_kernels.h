@@ -1,0 +1,589 @@
+// McMurchie-Davidson electron-repulsion kernels for one quartet class
+// (bra pair class (LA, LB), ket pair class (LC, LD)), with the on-the-fly
+// J/K digest of Eq. fock or a plain store of the contracted block.
+//
+// Per primitive quartet (bra primitive pair i, ket primitive pair j):
+//   alpha = p q / (p + q),  R_PQ = P - Q,  T = alpha |R_PQ|^2
+//   F_0..F_L(T)                                  (Boys, boys.h)
+//   R^n_000 = (-2 alpha)^n F_n(T) / sqrt(p + q)  (Eq. Rn-definition, source;
+//             the 1/sqrt(p+q) of the ERI prefactor rides along linearly)
+//   R^0_tuv by Eq. R-recursion, in place
+//   W_{tuv,cd} = sum_{tau nu phi} (-1)^{tau+nu+phi} E^{cd}_{tau nu phi} R^0_{t+tau,u+nu,v+phi}
+//   (ab|cd)   += sum_{tuv} E^{ab}_{tuv} W_{tuv,cd}
+// which is Eq. eri-tensor-contracted evaluated through the intermediate
+// J_{tuv,k} of Sec. 2.5.  The pair tables carry the contraction
+// coefficients and sqrt(2 pi^(5/2)) / p (resp. / q) of the prefactor of
+// Eq. twoe-final, so the sum is already the contracted integral.
+//
+// Digest of a canonical quartet (ab|cd) with value v and degeneracy factor
+// f = (1/2)^[a=b] (1/2)^[c=d] (1/2)^[ab=cd] into half-sums J', K':
+//   J'_ab += 2 f v D_cd   J'_cd += 2 f v D_ab
+//   K'_ac += f v D_bd     K'_bc += f v D_ad   K'_ad += f v D_bc   K'_bd += f v D_ac
+// so that J = J' + J'^T and K = K' + K'^T (the eight permutational images of
+// every canonical quartet then count once).
+#pragma once
+
+#include <utility>
+
+#include "boys.h"
+#include "fsim_internal.h"
+
+namespace fsim {
+
+template <typename F, int... I>
+__device__ __forceinline__ void static_for_impl(F &&f, std::integer_sequence<int, I...>) {
+    (f(std::integral_constant<int, I>{}), ...);
+}
+template <int N, typename F>
+__device__ __forceinline__ void static_for(F &&f) {
+    if constexpr (N > 0) static_for_impl(f, std::make_integer_sequence<int, N>{});
+}
+
+template <typename T>
+__device__ __forceinline__ const T *etab(const PairTable &t);
+template <>
+__device__ __forceinline__ const double *etab<double>(const PairTable &t) { return t.E; }
+template <>
+__device__ __forceinline__ const float *etab<float>(const PairTable &t) { return t.Ef; }
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+// In-place Hermite Coulomb recursion: on entry src[n] = R^n_000; on exit
+// r[hidx(t,u,v)] = R^0_tuv for t + u + v <= L.  At step n the totals are
+// rewritten from high to low, so every R^{n+1} value is read before its slot
+// is overwritten.
+template <int L, typename T>
+__device__ __forceinline__ void hermite_r(const T *src, T X, T Y, T Z, T *r) {
+    r[0] = src[L];
+    static_for<L>([&](auto m_) {
+        constexpr int n = L - 1 - decltype(m_)::value;
+        static_for<L - n>([&](auto k_) {
+            constexpr int s = L - n - decltype(k_)::value;
+            constexpr int base = s == 0 ? 0 : nherm(s - 1);
+            static_for<nherm(s) - base>([&](auto q_) {
+                constexpr int id = base + decltype(q_)::value;
+                constexpr int t = hidx_t(id), u = hidx_u(id), v = hidx_v(id);
+                if constexpr (t > 0) {
+                    if constexpr (t > 1)
+                        r[id] = X * r[hidx(t - 1, u, v)] + T(t - 1) * r[hidx(t - 2, u, v)];
+                    else
+                        r[id] = X * r[hidx(t - 1, u, v)];
+                } else if constexpr (u > 0) {
+                    if constexpr (u > 1)
+                        r[id] = Y * r[hidx(t, u - 1, v)] + T(u - 1) * r[hidx(t, u - 2, v)];
+                    else
+                        r[id] = Y * r[hidx(t, u - 1, v)];
+                } else {
+                    if constexpr (v > 1)
+                        r[id] = Z * r[hidx(t, u, v - 1)] + T(v - 1) * r[hidx(t, u, v - 2)];
+                    else
+                        r[id] = Z * r[hidx(t, u, v - 1)];
+                }
+            });
+        });
+        r[0] = src[n];
+    });
+}
+
+// Locate the tile's bra and ket range (Fock mode).  tile_start is the
+// prefix sum of tiles per bra; the search is wave-uniform.
+__device__ __forceinline__ int tile_bra(const TileList &tl, int tile) {
+    int lo = 0, hi = tl.nbra - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (tl.tile_start[mid] <= tile) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+// ===========================================================================
+// Kernel A: one lane per contracted quartet, everything unrolled at compile
+// time.  A wave owns a tile (one bra pair, up to 64 consecutive kets), so the
+// bra's exponents, centre and Hermite tensor are wave-uniform (scalar loads)
+// and the ket tables are read with unit stride across lanes.
+// ===========================================================================
+template <int LA, int LB, int LC, int LD, typename T, bool STORE>
+__global__ __launch_bounds__(256) void k_eri_lane(EriArgs a) {
+    constexpr int L = LA + LB + LC + LD, LAB = LA + LB;
+    constexpr int NA = ncart(LA), NB = ncart(LB), NC = ncart(LC), ND = ncart(LD);
+    constexpr int NAB = NA * NB, NCD = NC * ND, NHAB = nherm(LAB), NH = nherm(L);
+    constexpr int NEB = n_entries(LA, LB), NEK = n_entries(LC, LD);
+    __shared__ double tab[BOYS_LDS];
+    boys_stage(tab, a.boys, L);
+    __syncthreads();
+    const int lane = threadIdx.x & 63;
+    const int wpb = blockDim.x >> 6;
+    const int ntile = STORE ? a.st_ntile : a.tl.ntile;
+    const T *__restrict__ Eb = etab<T>(a.bra);
+    const T *__restrict__ Ek = etab<T>(a.ket);
+    const size_t nb = a.bra.n, nk = a.ket.n;
+
+    for (int tile0 = blockIdx.x * wpb + (threadIdx.x >> 6); tile0 < ntile;
+         tile0 += gridDim.x * wpb) {
+        const int tile = __builtin_amdgcn_readfirstlane(tile0);
+        int bra, ket;
+        bool active;
+        if constexpr (STORE) {
+            bra = __builtin_amdgcn_readfirstlane(a.st_bra[tile]);
+            ket = a.st_ket[tile * 64 + lane];
+            active = ket >= 0;
+            if (!active) ket = 0;
+        } else {
+            const int b = tile_bra(a.tl, tile);
+            bra = __builtin_amdgcn_readfirstlane(a.tl.bra[b]);
+            const int k0 = a.tl.ket_lo[b] + (tile - a.tl.tile_start[b]) * TILE;
+            ket = k0 + lane;
+            active = ket < a.tl.ket_hi[b];
+            if (!active) ket = k0;
+        }
+
+        T out[NAB][NCD];
+#pragma unroll
+        for (int x = 0; x < NAB; ++x)
+#pragma unroll
+            for (int y = 0; y < NCD; ++y) out[x][y] = T(0);
+
+        const int nbp = __builtin_amdgcn_readfirstlane(a.bra.nprim[bra]);
+        const int nkp = active ? a.ket.nprim[ket] : 0;
+        for (int i = 0; i < nbp; ++i) {
+            const double p = a.bra.p[i * nb + bra];
+            const double Px = a.bra.P[(i * 3 + 0) * nb + bra];
+            const double Py = a.bra.P[(i * 3 + 1) * nb + bra];
+            const double Pz = a.bra.P[(i * 3 + 2) * nb + bra];
+            const T *__restrict__ eb = Eb + (size_t)i * NEB * nb + bra;
+            for (int j = 0; j < nkp; ++j) {
+                const double q = a.ket.p[j * nk + ket];
+                const double X = Px - a.ket.P[(j * 3 + 0) * nk + ket];
+                const double Y = Py - a.ket.P[(j * 3 + 1) * nk + ket];
+                const double Z = Pz - a.ket.P[(j * 3 + 2) * nk + ket];
+                const double pq = p + q, alpha = p * q / pq;
+                double F[L + 1];
+                boys_eval<L>(alpha * (X * X + Y * Y + Z * Z), tab, F);
+                T src[L + 1];
+                double m = 1.0 / sqrt(pq);
+#pragma unroll
+                for (int n = 0; n <= L; ++n) {
+                    src[n] = T(F[n] * m);
+                    m *= -2.0 * alpha;
+                }
+                T r[NH];
+                hermite_r<L, T>(src, T(X), T(Y), T(Z), r);
+                const T *__restrict__ ek = Ek + (size_t)j * NEK * nk + ket;
+                static_for<NCD>([&](auto cd_) {
+                    constexpr int cd = decltype(cd_)::value;
+                    constexpr int bx = box_dim(LC, LD, cd, 0), by = box_dim(LC, LD, cd, 1),
+                                  bz = box_dim(LC, LD, cd, 2);
+                    constexpr int eo = box_off(LC, LD, cd);
+                    T w[NHAB];
+#pragma unroll
+                    for (int h = 0; h < NHAB; ++h) w[h] = T(0);
+                    static_for<bx + 1>([&](auto ta_) {
+                        constexpr int ta = decltype(ta_)::value;
+                        static_for<by + 1>([&](auto nu_) {
+                            constexpr int nu = decltype(nu_)::value;
+                            static_for<bz + 1>([&](auto ph_) {
+                                constexpr int ph = decltype(ph_)::value;
+                                constexpr int e = eo + (ta * (by + 1) + nu) * (bz + 1) + ph;
+                                T ev = ek[(size_t)e * nk];
+                                if constexpr ((ta + nu + ph) & 1) ev = -ev;
+                                static_for<NHAB>([&](auto h_) {
+                                    constexpr int h = decltype(h_)::value;
+                                    constexpr int ri = hidx(hidx_t(h) + ta, hidx_u(h) + nu,
+                                                            hidx_v(h) + ph);
+                                    w[h] = fma(ev, r[ri], w[h]);
+                                });
+                            });
+                        });
+                    });
+                    static_for<NAB>([&](auto ab_) {
+                        constexpr int ab = decltype(ab_)::value;
+                        constexpr int ax = box_dim(LA, LB, ab, 0), ay = box_dim(LA, LB, ab, 1),
+                                      az = box_dim(LA, LB, ab, 2);
+                        constexpr int ao = box_off(LA, LB, ab);
+                        T acc = out[ab][cd];
+                        static_for<ax + 1>([&](auto t_) {
+                            constexpr int t = decltype(t_)::value;
+                            static_for<ay + 1>([&](auto u_) {
+                                constexpr int u = decltype(u_)::value;
+                                static_for<az + 1>([&](auto v_) {
+                                    constexpr int v = decltype(v_)::value;
+                                    constexpr int e = ao + (t * (ay + 1) + u) * (az + 1) + v;
+                                    acc = fma(eb[(size_t)e * nb], w[hidx(t, u, v)], acc);
+                                });
+                            });
+                        });
+                        out[ab][cd] = acc;
+                    });
+                });
+            }
+        }
+
+        if constexpr (STORE) {
+            if (active) {
+                const size_t q = (size_t)tile * 64 + lane;
+                const long long off = a.st_off[q];
+                const int s0 = a.st_stride[q * 4 + 0], s1 = a.st_stride[q * 4 + 1],
+                          s2 = a.st_stride[q * 4 + 2], s3 = a.st_stride[q * 4 + 3];
+#pragma unroll
+                for (int ia = 0; ia < NA; ++ia)
+#pragma unroll
+                    for (int ib = 0; ib < NB; ++ib)
+#pragma unroll
+                        for (int ic = 0; ic < NC; ++ic)
+#pragma unroll
+                            for (int id = 0; id < ND; ++id)
+                                a.out[off + ia * s0 + ib * s1 + ic * s2 + id * s3] =
+                                    (double)out[ia * NB + ib][ic * ND + id];
+            }
+        } else {
+            const int N = a.nbf;
+            const int f1 = __builtin_amdgcn_readfirstlane(a.bra.bf1[bra]);
+            const int f2 = __builtin_amdgcn_readfirstlane(a.bra.bf2[bra]);
+            const int f3 = a.ket.bf1[ket], f4 = a.ket.bf2[ket];
+            double fac = active ? 1.0 : 0.0;
+            if (a.bra.sh1[bra] == a.bra.sh2[bra]) fac *= 0.5;
+            if (a.ket.sh1[ket] == a.ket.sh2[ket]) fac *= 0.5;
+            if (a.same_class && ket == bra) fac *= 0.5;
+            const double *__restrict__ D = a.D;
+            // J'_ab: pre-reduced over the wave, one atomic per component
+#pragma unroll
+            for (int ia = 0; ia < NA; ++ia)
+#pragma unroll
+                for (int ib = 0; ib < NB; ++ib) {
+                    double s = 0.0;
+#pragma unroll
+                    for (int ic = 0; ic < NC; ++ic)
+#pragma unroll
+                        for (int id = 0; id < ND; ++id)
+                            s += (double)out[ia * NB + ib][ic * ND + id] *
+                                 D[(size_t)(f3 + ic) * N + f4 + id];
+                    s = wave_sum(2.0 * fac * s);
+                    if (lane == 0) atomicAdd(&a.Jh[(size_t)(f1 + ia) * N + f2 + ib], s);
+                }
+            if (active) {
+#pragma unroll
+                for (int ic = 0; ic < NC; ++ic)
+#pragma unroll
+                    for (int id = 0; id < ND; ++id) {
+                        double s = 0.0;
+#pragma unroll
+                        for (int ia = 0; ia < NA; ++ia)
+#pragma unroll
+                            for (int ib = 0; ib < NB; ++ib)
+                                s += (double)out[ia * NB + ib][ic * ND + id] *
+                                     D[(size_t)(f1 + ia) * N + f2 + ib];
+                        atomicAdd(&a.Jh[(size_t)(f3 + ic) * N + f4 + id], 2.0 * fac * s);
+                    }
+#pragma unroll
+                for (int ia = 0; ia < NA; ++ia)
+#pragma unroll
+                    for (int ic = 0; ic < NC; ++ic) {
+                        double s = 0.0;
+#pragma unroll
+                        for (int ib = 0; ib < NB; ++ib)
+#pragma unroll
+                            for (int id = 0; id < ND; ++id)
+                                s += (double)out[ia * NB + ib][ic * ND + id] *
+                                     D[(size_t)(f2 + ib) * N + f4 + id];
+                        atomicAdd(&a.Kh[(size_t)(f1 + ia) * N + f3 + ic], fac * s);
+                    }
+#pragma unroll
+                for (int ib = 0; ib < NB; ++ib)
+#pragma unroll
+                    for (int ic = 0; ic < NC; ++ic) {
+                        double s = 0.0;
+#pragma unroll
+                        for (int ia = 0; ia < NA; ++ia)
+#pragma unroll
+                            for (int id = 0; id < ND; ++id)
+                                s += (double)out[ia * NB + ib][ic * ND + id] *
+                                     D[(size_t)(f1 + ia) * N + f4 + id];
+                        atomicAdd(&a.Kh[(size_t)(f2 + ib) * N + f3 + ic], fac * s);
+                    }
+#pragma unroll
+                for (int ia = 0; ia < NA; ++ia)
+#pragma unroll
+                    for (int id = 0; id < ND; ++id) {
+                        double s = 0.0;
+#pragma unroll
+                        for (int ib = 0; ib < NB; ++ib)
+#pragma unroll
+                            for (int ic = 0; ic < NC; ++ic)
+                                s += (double)out[ia * NB + ib][ic * ND + id] *
+                                     D[(size_t)(f2 + ib) * N + f3 + ic];
+                        atomicAdd(&a.Kh[(size_t)(f1 + ia) * N + f4 + id], fac * s);
+                    }
+#pragma unroll
+                for (int ib = 0; ib < NB; ++ib)
+#pragma unroll
+                    for (int id = 0; id < ND; ++id) {
+                        double s = 0.0;
+#pragma unroll
+                        for (int ia = 0; ia < NA; ++ia)
+#pragma unroll
+                            for (int ic = 0; ic < NC; ++ic)
+                                s += (double)out[ia * NB + ib][ic * ND + id] *
+                                     D[(size_t)(f1 + ia) * N + f3 + ic];
+                        atomicAdd(&a.Kh[(size_t)(f2 + ib) * N + f4 + id], fac * s);
+                    }
+            }
+        }
+    }
+}
+
+// ===========================================================================
+// Kernel B: one wave per contracted quartet for the high-L classes (d shells).
+// R^0 is built level by level in LDS with the lanes over Hermite triples,
+// W_{tuv,cd} is accumulated over ket primitives with the lanes over
+// (tuv, cd), and the block with the lanes over (ab, cd).
+// ===========================================================================
+template <int LA, int LB, int LC, int LD, typename T, bool STORE>
+__global__ __launch_bounds__(64) void k_eri_wave(EriArgs a) {
+    constexpr int L = LA + LB + LC + LD, LAB = LA + LB;
+    constexpr int NA = ncart(LA), NB = ncart(LB), NC = ncart(LC), ND = ncart(LD);
+    constexpr int NAB = NA * NB, NCD = NC * ND, NHAB = nherm(LAB), NH = nherm(L);
+    constexpr int NEB = n_entries(LA, LB), NEK = n_entries(LC, LD);
+    constexpr int NW = NHAB * NCD, NWL = (NW + 63) / 64;
+    constexpr int NO = NAB * NCD, NOL = (NO + 63) / 64;
+    constexpr int NRL = (NH + 63) / 64;
+    __shared__ double tab[BOYS_LDS];
+    __shared__ T rbuf[2][NH];
+    __shared__ T wl[NW];
+    __shared__ T ebl[NEB], ekl[NEK];
+    boys_stage(tab, a.boys, L);
+    const int lane = threadIdx.x;
+
+    // per-lane decode of the owned Hermite triples, W entries and block entries
+    int rt[NRL], ru[NRL], rv[NRL];
+#pragma unroll
+    for (int k = 0; k < NRL; ++k) {
+        const int id = lane + 64 * k < NH ? lane + 64 * k : 0;
+        rt[k] = hidx_t(id);
+        ru[k] = hidx_u(id);
+        rv[k] = hidx_v(id);
+    }
+    int wt[NWL], wu[NWL], wv[NWL], wcd[NWL], wbx[NWL], wby[NWL], wbz[NWL], wo[NWL];
+#pragma unroll
+    for (int k = 0; k < NWL; ++k) {
+        const int e = lane + 64 * k < NW ? lane + 64 * k : 0;
+        const int h = e / NCD, cd = e % NCD;
+        wt[k] = hidx_t(h);
+        wu[k] = hidx_u(h);
+        wv[k] = hidx_v(h);
+        wcd[k] = cd;
+        wbx[k] = box_dim(LC, LD, cd, 0);
+        wby[k] = box_dim(LC, LD, cd, 1);
+        wbz[k] = box_dim(LC, LD, cd, 2);
+        wo[k] = box_off(LC, LD, cd);
+    }
+    int oab[NOL], ocd[NOL], obx[NOL], oby[NOL], obz[NOL], oo[NOL];
+#pragma unroll
+    for (int k = 0; k < NOL; ++k) {
+        const int e = lane + 64 * k < NO ? lane + 64 * k : 0;
+        oab[k] = e / NCD;
+        ocd[k] = e % NCD;
+        obx[k] = box_dim(LA, LB, oab[k], 0);
+        oby[k] = box_dim(LA, LB, oab[k], 1);
+        obz[k] = box_dim(LA, LB, oab[k], 2);
+        oo[k] = box_off(LA, LB, oab[k]);
+    }
+    __syncthreads();
+
+    const int ntile = STORE ? a.st_ntile : a.tl.ntile;
+    const T *__restrict__ Eb = etab<T>(a.bra);
+    const T *__restrict__ Ek = etab<T>(a.ket);
+    const size_t nb = a.bra.n, nk = a.ket.n;
+
+    for (int tile = blockIdx.x; tile < ntile; tile += gridDim.x) {
+        int bra, k0 = 0, k1 = 0;
+        if constexpr (STORE) {
+            bra = a.st_bra[tile];
+            k1 = 64;
+        } else {
+            const int b = tile_bra(a.tl, tile);
+            bra = a.tl.bra[b];
+            k0 = a.tl.ket_lo[b] + (tile - a.tl.tile_start[b]) * TILE;
+            k1 = min(k0 + TILE, a.tl.ket_hi[b]);
+        }
+        const int nbp = a.bra.nprim[bra];
+        for (int kk = k0; kk < k1; ++kk) {
+            int ket = kk;
+            if constexpr (STORE) {
+                ket = a.st_ket[tile * 64 + kk];
+                if (ket < 0) continue;
+            }
+            const int nkp = a.ket.nprim[ket];
+            T o[NOL];
+#pragma unroll
+            for (int k = 0; k < NOL; ++k) o[k] = T(0);
+            for (int i = 0; i < nbp; ++i) {
+                const double p = a.bra.p[i * nb + bra];
+                const double Px = a.bra.P[(i * 3 + 0) * nb + bra];
+                const double Py = a.bra.P[(i * 3 + 1) * nb + bra];
+                const double Pz = a.bra.P[(i * 3 + 2) * nb + bra];
+                for (int e = lane; e < NEB; e += 64) ebl[e] = Eb[((size_t)i * NEB + e) * nb + bra];
+                T w[NWL];
+#pragma unroll
+                for (int k = 0; k < NWL; ++k) w[k] = T(0);
+                for (int j = 0; j < nkp; ++j) {
+                    const double q = a.ket.p[j * nk + ket];
+                    const double X = Px - a.ket.P[(j * 3 + 0) * nk + ket];
+                    const double Y = Py - a.ket.P[(j * 3 + 1) * nk + ket];
+                    const double Z = Pz - a.ket.P[(j * 3 + 2) * nk + ket];
+                    const double pq = p + q, alpha = p * q / pq;
+                    double F[L + 1];
+                    boys_eval<L>(alpha * (X * X + Y * Y + Z * Z), tab, F);
+                    T src[L + 1];
+                    double m = 1.0 / sqrt(pq);
+#pragma unroll
+                    for (int n = 0; n <= L; ++n) {
+                        src[n] = T(F[n] * m);
+                        m *= -2.0 * alpha;
+                    }
+                    for (int e = lane; e < NEK; e += 64)
+                        ekl[e] = Ek[((size_t)j * NEK + e) * nk + ket];
+                    // R^0 level by level (level n holds totals <= L - n)
+                    int cur = 0;
+                    if (lane == 0) rbuf[0][0] = src[L];
+                    __syncthreads();
+                    for (int n = L - 1; n >= 0; --n) {
+                        const int nxt = cur ^ 1, cnt = nherm(L - n);
+                        const T Xt = T(X), Yt = T(Y), Zt = T(Z);
+#pragma unroll
+                        for (int k = 0; k < NRL; ++k) {
+                            const int id = lane + 64 * k;
+                            if (id < cnt) {
+                                const int t = rt[k], u = ru[k], v = rv[k];
+                                T val;
+                                if (id == 0) val = src[n];
+                                else if (t > 0)
+                                    val = Xt * rbuf[cur][hidx(t - 1, u, v)] +
+                                          (t > 1 ? T(t - 1) * rbuf[cur][hidx(t - 2, u, v)] : T(0));
+                                else if (u > 0)
+                                    val = Yt * rbuf[cur][hidx(t, u - 1, v)] +
+                                          (u > 1 ? T(u - 1) * rbuf[cur][hidx(t, u - 2, v)] : T(0));
+                                else
+                                    val = Zt * rbuf[cur][hidx(t, u, v - 1)] +
+                                          (v > 1 ? T(v - 1) * rbuf[cur][hidx(t, u, v - 2)] : T(0));
+                                rbuf[nxt][id] = val;
+                            }
+                        }
+                        cur = nxt;
+                        __syncthreads();
+                    }
+                    const T *R = rbuf[cur];
+#pragma unroll
+                    for (int k = 0; k < NWL; ++k) {
+                        if (lane + 64 * k < NW) {
+                            T acc = w[k];
+                            int e = wo[k];
+                            for (int ta = 0; ta <= wbx[k]; ++ta)
+                                for (int nu = 0; nu <= wby[k]; ++nu)
+                                    for (int ph = 0; ph <= wbz[k]; ++ph, ++e) {
+                                        const T ev = ((ta + nu + ph) & 1) ? -ekl[e] : ekl[e];
+                                        acc += ev * R[hidx(wt[k] + ta, wu[k] + nu, wv[k] + ph)];
+                                    }
+                            w[k] = acc;
+                        }
+                    }
+                    __syncthreads();
+                }
+#pragma unroll
+                for (int k = 0; k < NWL; ++k)
+                    if (lane + 64 * k < NW) wl[lane + 64 * k] = w[k];
+                __syncthreads();
+#pragma unroll
+                for (int k = 0; k < NOL; ++k) {
+                    if (lane + 64 * k < NO) {
+                        T acc = o[k];
+                        int e = oo[k];
+                        for (int t = 0; t <= obx[k]; ++t)
+                            for (int u = 0; u <= oby[k]; ++u)
+                                for (int v = 0; v <= obz[k]; ++v, ++e)
+                                    acc += ebl[e] * wl[hidx(t, u, v) * NCD + ocd[k]];
+                        o[k] = acc;
+                    }
+                }
+                __syncthreads();
+            }
+            // write out or digest
+            if constexpr (STORE) {
+                const size_t q = (size_t)tile * 64 + kk;
+                const long long off = a.st_off[q];
+                const int s0 = a.st_stride[q * 4 + 0], s1 = a.st_stride[q * 4 + 1],
+                          s2 = a.st_stride[q * 4 + 2], s3 = a.st_stride[q * 4 + 3];
+#pragma unroll
+                for (int k = 0; k < NOL; ++k) {
+                    if (lane + 64 * k < NO) {
+                        const int ia = oab[k] / NB, ib = oab[k] % NB, ic = ocd[k] / ND,
+                                  id = ocd[k] % ND;
+                        a.out[off + ia * s0 + ib * s1 + ic * s2 + id * s3] = (double)o[k];
+                    }
+                }
+            } else {
+                const int N = a.nbf;
+                const int f1 = a.bra.bf1[bra], f2 = a.bra.bf2[bra];
+                const int f3 = a.ket.bf1[ket], f4 = a.ket.bf2[ket];
+                double fac = 1.0;
+                if (a.bra.sh1[bra] == a.bra.sh2[bra]) fac *= 0.5;
+                if (a.ket.sh1[ket] == a.ket.sh2[ket]) fac *= 0.5;
+                if (a.same_class && ket == bra) fac *= 0.5;
+                const double *__restrict__ D = a.D;
+#pragma unroll
+                for (int k = 0; k < NOL; ++k) {
+                    if (lane + 64 * k < NO) {
+                        const size_t I = f1 + oab[k] / NB, J = f2 + oab[k] % NB,
+                                     K = f3 + ocd[k] / ND, M = f4 + ocd[k] % ND;
+                        const double v = fac * (double)o[k];
+                        atomicAdd(&a.Jh[I * N + J], 2.0 * v * D[K * N + M]);
+                        atomicAdd(&a.Jh[K * N + M], 2.0 * v * D[I * N + J]);
+                        atomicAdd(&a.Kh[I * N + K], v * D[J * N + M]);
+                        atomicAdd(&a.Kh[J * N + K], v * D[I * N + M]);
+                        atomicAdd(&a.Kh[I * N + M], v * D[J * N + K]);
+                        atomicAdd(&a.Kh[J * N + M], v * D[I * N + K]);
+                    }
+                }
+            }
+        }
+    }
+}
+
+// Launch one class.  Kernel A for L <= 4, kernel B above.
+template <int LA, int LB, int LC, int LD>
+hipError_t launch_class(bool fp32, bool store, const EriArgs &a, hipStream_t s) {
+    const int ntile = store ? a.st_ntile : a.tl.ntile;
+    if (ntile <= 0) return hipSuccess;
+    constexpr int L = LA + LB + LC + LD;
+    if constexpr (L <= 4) {
+        const int wpb = 4;
+        int blocks = (ntile + wpb - 1) / wpb;
+        if (blocks > 8192) blocks = 8192;
+        dim3 g(blocks), b(64 * wpb);
+        if (fp32) {
+            if (store) hipLaunchKernelGGL((k_eri_lane<LA, LB, LC, LD, float, true>), g, b, 0, s, a);
+            else hipLaunchKernelGGL((k_eri_lane<LA, LB, LC, LD, float, false>), g, b, 0, s, a);
+        } else {
+            if (store) hipLaunchKernelGGL((k_eri_lane<LA, LB, LC, LD, double, true>), g, b, 0, s, a);
+            else hipLaunchKernelGGL((k_eri_lane<LA, LB, LC, LD, double, false>), g, b, 0, s, a);
+        }
+    } else {
+        int blocks = ntile;
+        if (blocks > 32768) blocks = 32768;
+        dim3 g(blocks), b(64);
+        if (fp32) {
+            if (store) hipLaunchKernelGGL((k_eri_wave<LA, LB, LC, LD, float, true>), g, b, 0, s, a);
+            else hipLaunchKernelGGL((k_eri_wave<LA, LB, LC, LD, float, false>), g, b, 0, s, a);
+        } else {
+            if (store) hipLaunchKernelGGL((k_eri_wave<LA, LB, LC, LD, double, true>), g, b, 0, s, a);
+            else hipLaunchKernelGGL((k_eri_wave<LA, LB, LC, LD, double, false>), g, b, 0, s, a);
+        }
+    }
+    return hipGetLastError();
+}
+
+}  // namespace fsim

@@ -1,0 +1,188 @@
+// Internal declarations of libfsim: compile-time index algebra of Cartesian
+// and Hermite components, device-side table layouts and kernel launch
+// records.  Shared by the HIP sources of the library only.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+namespace fsim {
+
+constexpr int LMAX = 2;                // s, p, Cartesian d
+constexpr int LTOT_MAX = 4 * LMAX;     // highest L of a shell quartet
+constexpr int MAXPRIM = 8;             // primitives per shell
+constexpr int NPCLASS = 6;             // pair classes ss ps pp ds dp dd
+
+// ---- Boys-function grid ------------------------------------------------
+// F_n(T_k) is tabulated at T_k = k * BOYS_DT for k < BOYS_NT and
+// n < BOYS_NORD; below BOYS_TMAX a class of total L evaluates F_L by an
+// 8-term Taylor expansion about the nearest grid point (|dT| <= 0.05, so the
+// truncation error is below dT^8 / 8! ~ 1e-15 relative) and the lower orders
+// by the downward recursion; from BOYS_TMAX on, F_0 = sqrt(pi / T) / 2 and
+// the upward recursion (exact up to erfc(6) ~ 2e-17).
+constexpr double BOYS_DT = 0.1;
+constexpr double BOYS_INV_DT = 10.0;
+constexpr double BOYS_TMAX = 36.0;
+constexpr int BOYS_NT = 361;
+constexpr int BOYS_NTAYLOR = 8;
+constexpr int BOYS_NORD = LTOT_MAX + BOYS_NTAYLOR;   // orders 0..15
+
+// ---- component algebra -------------------------------------------------
+__host__ __device__ constexpr int ncart(int l) { return (l + 1) * (l + 2) / 2; }
+__host__ __device__ constexpr int nherm(int L) { return (L + 1) * (L + 2) * (L + 3) / 6; }
+
+// Cartesian exponent of component c of a shell with angular momentum l in
+// direction dir (0 = x, 1 = y, 2 = z); components run lx descending, then ly
+// descending.
+__host__ __device__ constexpr int cart_exp(int l, int c, int dir) {
+    int k = 0;
+    for (int x = l; x >= 0; --x)
+        for (int y = l - x; y >= 0; --y) {
+            if (k == c) return dir == 0 ? x : (dir == 1 ? y : l - x - y);
+            ++k;
+        }
+    return 0;
+}
+
+// Linear index of the Hermite triple (t, u, v): graded by s = t + u + v, so
+// the first nherm(L) slots hold every triple of total <= L for any L.
+__host__ __device__ constexpr int hidx(int t, int u, int v) {
+    int s = t + u + v, a = u + v;
+    return s * (s + 1) * (s + 2) / 6 + a * (a + 1) / 2 + v;
+}
+__host__ __device__ constexpr int hidx_t(int i) {
+    int s = 0;
+    while (nherm(s) <= i) ++s;
+    int r = i - (s == 0 ? 0 : nherm(s - 1));
+    int a = 0;
+    while ((a + 1) * (a + 2) / 2 <= r) ++a;
+    return s - a;
+}
+__host__ __device__ constexpr int hidx_v(int i) {
+    int s = 0;
+    while (nherm(s) <= i) ++s;
+    int r = i - (s == 0 ? 0 : nherm(s - 1));
+    int a = 0;
+    while ((a + 1) * (a + 2) / 2 <= r) ++a;
+    return r - a * (a + 1) / 2;
+}
+__host__ __device__ constexpr int hidx_u(int i) {
+    int s = 0;
+    while (nherm(s) <= i) ++s;
+    return s - hidx_t(i) - hidx_v(i);
+}
+
+// Hermite box of the component pair cp = c1 * ncart(l2) + c2 of a shell pair
+// (l1, l2): E^{c1 c2}_{tuv} is non-zero only for t <= bx, u <= by, v <= bz.
+__host__ __device__ constexpr int box_dim(int l1, int l2, int cp, int dir) {
+    return cart_exp(l1, cp / ncart(l2), dir) + cart_exp(l2, cp % ncart(l2), dir);
+}
+__host__ __device__ constexpr int box_size(int l1, int l2, int cp) {
+    return (box_dim(l1, l2, cp, 0) + 1) * (box_dim(l1, l2, cp, 1) + 1) *
+           (box_dim(l1, l2, cp, 2) + 1);
+}
+// Offset of component pair cp's box in the per-primitive-pair entry list.
+__host__ __device__ constexpr int box_off(int l1, int l2, int cp) {
+    int o = 0;
+    for (int k = 0; k < cp; ++k) o += box_size(l1, l2, k);
+    return o;
+}
+// Entries per primitive pair of class (l1, l2).
+__host__ __device__ constexpr int n_entries(int l1, int l2) {
+    return box_off(l1, l2, ncart(l1) * ncart(l2));
+}
+
+__host__ __device__ constexpr int pclass(int l1, int l2) {   // l1 >= l2
+    return l1 * (l1 + 1) / 2 + l2;
+}
+inline int pclass_l1(int pc) { return pc < 1 ? 0 : (pc < 3 ? 1 : 2); }
+inline int pclass_l2(int pc) { return pc - pclass(pclass_l1(pc), 0); }
+
+// ---- device tables -------------------------------------------------------
+// One shell-pair class (l1 >= l2).  Pairs are stored column-wise (pair index
+// fastest) so that lanes handling consecutive pairs read consecutive words.
+// Each primitive pair slot k < kmax holds the product exponent p, the centre
+// P and the Hermite box entries
+//   E[k][e][pair] = c1 c2 n1 n2 sqrt(2) pi^(5/4) / p * E^{i1 j1}_t E^{i2 j2}_u E^{i3 j3}_v
+// (contraction coefficients, component normalisation and the pair's share of
+// the ERI prefactor 2 pi^(5/2) / (p q sqrt(p + q)) folded in).
+struct PairTable {
+    int n = 0;        // pairs
+    int kmax = 0;     // primitive-pair slots
+    int ne = 0;       // box entries per primitive pair
+    int l1 = 0, l2 = 0;
+    int *sh1 = nullptr, *sh2 = nullptr;   // shell indices (l(sh1) >= l(sh2))
+    int *bf1 = nullptr, *bf2 = nullptr;   // first basis function of each shell
+    int *nprim = nullptr;                 // primitive pairs in use
+    double *Q = nullptr;                  // Schwarz factor
+    double *p = nullptr;                  // [kmax][n]
+    double *P = nullptr;                  // [kmax][3][n]
+    double *E = nullptr;                  // [kmax][ne][n]
+    float *Ef = nullptr;                  // FP32 copy of E
+};
+
+// Tile lists of one quartet class and precision: bra pair b owns the ket
+// range [ket_lo[b], ket_hi[b]) cut into tiles of TILE kets.
+struct TileList {
+    int nbra = 0;
+    int ntile = 0;
+    int64_t nquartet = 0;
+    int *tile_start = nullptr;   // [nbra + 1]
+    int *bra = nullptr;          // [nbra]
+    int *ket_lo = nullptr;       // [nbra]
+    int *ket_hi = nullptr;       // [nbra]
+};
+
+constexpr int TILE = 64;   // kets per wave tile (one per lane)
+
+struct EriArgs {
+    PairTable bra, ket;
+    int same_class;
+    // Fock mode
+    TileList tl;
+    const double *D;
+    double *Jh;
+    double *Kh;
+    int nbf;
+    // store mode: tile t has bra st_bra[t]; lane l evaluates ket st_ket[t*64+l]
+    // (-1 = idle) and writes component (i,j,k,l) to
+    // out[st_off + i*s0 + j*s1 + k*s2 + l*s3]
+    int st_ntile;
+    const int *st_bra;
+    const int *st_ket;
+    const long long *st_off;
+    const int *st_stride;   // [4 per task]
+    double *out;
+    const double *boys;     // [BOYS_NT][BOYS_NORD]
+};
+
+
+// setup kernels (setup.hip)
+hipError_t launch_boys_table(double *tab, hipStream_t s);
+struct ShellsDev {
+    int nshell = 0, natom = 0;
+    double *xyz = nullptr;     // [nshell][3] centre of each shell
+    int *l = nullptr, *nprim = nullptr, *prim0 = nullptr, *bf0 = nullptr;
+    double *exps = nullptr;
+    double *coef = nullptr;    // normalised (radial norm x contraction renorm)
+    double *atom_xyz = nullptr;
+    double *atom_Z = nullptr;
+};
+hipError_t launch_shell_norm(const ShellsDev &sh, hipStream_t s);
+hipError_t launch_build_pairs(const ShellsDev &sh, PairTable &t, const int *pair_sh1,
+                              const int *pair_sh2, hipStream_t s);
+hipError_t launch_one_electron_impl(const ShellsDev &sh, const double *boys, int nbf,
+                                    const int *bf_shell, const int *bf_comp, double *S,
+                                    double *T, double *V, hipStream_t s);
+// per-bra-class launchers (eri_b<pc>.hip)
+hipError_t launch_eri_bra0(int ket_pc, bool fp32, bool store, const EriArgs &a, hipStream_t s);
+hipError_t launch_eri_bra1(int ket_pc, bool fp32, bool store, const EriArgs &a, hipStream_t s);
+hipError_t launch_eri_bra2(int ket_pc, bool fp32, bool store, const EriArgs &a, hipStream_t s);
+hipError_t launch_eri_bra3(int ket_pc, bool fp32, bool store, const EriArgs &a, hipStream_t s);
+hipError_t launch_eri_bra4(int ket_pc, bool fp32, bool store, const EriArgs &a, hipStream_t s);
+hipError_t launch_eri_bra5(int ket_pc, bool fp32, bool store, const EriArgs &a, hipStream_t s);
+
+}  // namespace fsim

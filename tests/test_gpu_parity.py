@@ -1,0 +1,285 @@
+"""GPU path against the FP64 oracle, through the C ABI (libfsim.so).
+
+Tolerances: per contracted ERI 1e-12 absolute in FP64; J and K elements
+1e-11 absolute (they sum up to ~1e6 integrals whose atomic accumulation
+order varies); energies 1e-8 Ha (FP64) and 1e-6 Ha (mixed precision)."""
+
+import itertools
+import json
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from helpers import custom_basis, spd_molecule
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+
+
+def _fsim():
+    from paper_2510_24968_amd import fsim
+    return fsim
+
+
+def _ctx(basis, **kw):
+    print(f"[gpu] context {basis.get('name', '?')} {kw}", flush=True)
+    return _fsim().Context(basis, **kw)
+
+
+def _random_density(N, seed):
+    rng = np.random.default_rng(seed)
+    A = rng.standard_normal((N, N))
+    return 0.5 * (A + A.T)
+
+
+def _dev(a):
+    return torch.tensor(np.ascontiguousarray(a), dtype=torch.float64, device="cuda")
+
+
+# ---------------------------------------------------------------------------
+# integrals
+# ---------------------------------------------------------------------------
+
+
+def test_h8_every_canonical_quartet():
+    b = synth.h_chain(8, 1.4)
+    ctx = _ctx(b)
+    B = oracle.Basis(b)
+    ns = B.nshell
+    quartets = [(a, bb, c, d) for a in range(ns) for bb in range(a + 1) for c in range(ns)
+                for d in range(c + 1) if a * (a + 1) // 2 + bb >= c * (c + 1) // 2 + d]
+    assert len(quartets) == 666
+    got = ctx.eri_quartets(quartets)
+    err = max(np.max(np.abs(g - B.eri_block(*q))) for g, q in zip(got, quartets))
+    print("h8 max |dERI| =", err)
+    assert err < 1e-12
+
+
+def test_every_class_and_orientation():
+    """All ordered shell quartets of a 3-centre s/p/d molecule with mixed
+    contraction lengths: every one of the 21 quartet classes, in every
+    bra/ket and within-pair orientation."""
+    b = spd_molecule()
+    ctx = _ctx(b)
+    B = oracle.Basis(b)
+    ns = B.nshell
+    quartets = list(itertools.product(range(ns), repeat=4))
+    got = ctx.eri_quartets(quartets)
+    worst = 0.0
+    for g, q in zip(got, quartets):
+        ref = B.eri_block(*q)
+        worst = max(worst, float(np.max(np.abs(g - ref))))
+    print("spd max |dERI| =", worst)
+    assert worst < 1e-12
+
+
+def test_fp32_blocks_are_close():
+    b = spd_molecule()
+    ctx = _ctx(b)
+    B = oracle.Basis(b)
+    ns = B.nshell
+    quartets = list(itertools.product(range(ns), repeat=4))[::7]
+    got = ctx.eri_quartets(quartets, precision="mixed")
+    for g, q in zip(got, quartets):
+        ref = B.eri_block(*q)
+        scale = max(1.0, float(np.max(np.abs(ref))))
+        assert np.max(np.abs(g - ref)) < 2e-5 * scale, q
+
+
+def test_one_electron_and_orthogonaliser():
+    for b in (spd_molecule(), synth.water_cluster(2, 0)):
+        ctx = _ctx(b)
+        S, H, X = [t.cpu().numpy() for t in ctx.one_electron()]
+        So, To, Vo = oracle.Basis(b).one_electron()
+        assert np.max(np.abs(S - So)) < 1e-13
+        assert np.max(np.abs(H - (To + Vo))) < 1e-11
+        assert np.max(np.abs(X @ S @ X - np.eye(len(S)))) < 1e-10
+        assert ctx.enuc == pytest.approx(oracle.Basis(b).nuclear_repulsion(), rel=1e-14)
+
+
+def test_schwarz_factors():
+    b = synth.water_cluster(3, 1)
+    ctx = _ctx(b)
+    Q, st = ctx.schwarz_screen(tau=1e-10)
+    Qo = oracle.Basis(b).schwarz()
+    assert np.allclose(Q.cpu().numpy(), Qo, rtol=1e-12, atol=1e-15)
+    ns = len(Qo)
+    assert st["shell_pairs"] == ns * (ns + 1) // 2
+
+
+# ---------------------------------------------------------------------------
+# Fock build (J, K, F, E)
+# ---------------------------------------------------------------------------
+
+
+def test_jk_unscreened_random_density():
+    b = synth.water_cluster(2, 0)
+    ctx = _ctx(b)
+    ctx.schwarz_screen(tau=0.0)
+    D = _random_density(ctx.nbf, 1)
+    r = ctx.fock_build(_dev(D), want_jk=True)
+    J, K = r["J"].cpu().numpy(), r["K"].cpu().numpy()
+    Jo, Ko = oracle.Basis(b).fock_jk(D, tau=0.0)
+    print("water2 |dJ|, |dK| =", np.max(np.abs(J - Jo)), np.max(np.abs(K - Ko)))
+    assert np.max(np.abs(J - Jo)) < 1e-11
+    assert np.max(np.abs(K - Ko)) < 1e-11
+
+
+def test_jk_spd_all_classes():
+    b = spd_molecule()
+    ctx = _ctx(b)
+    ctx.schwarz_screen(tau=0.0)
+    D = _random_density(ctx.nbf, 2)
+    r = ctx.fock_build(_dev(D), want_jk=True)
+    Jo, Ko = oracle.Basis(b).fock_jk(D, tau=0.0)
+    assert np.max(np.abs(r["J"].cpu().numpy() - Jo)) < 1e-11
+    assert np.max(np.abs(r["K"].cpu().numpy() - Ko)) < 1e-11
+    S, H, X = [t.cpu().numpy() for t in ctx.one_electron()]
+    F = r["F"].cpu().numpy()
+    assert np.max(np.abs(F - (H + Jo - 0.5 * Ko))) < 1e-11
+    assert r["E_elec"] == pytest.approx(0.5 * np.sum(D * (H + F)), abs=1e-10)
+
+
+def test_jk_screened_counts_and_values():
+    b = synth.water_cluster(3, 2)
+    tau = 1e-9
+    ctx = _ctx(b)
+    _, st = ctx.schwarz_screen(tau=tau)
+    B = oracle.Basis(b)
+    S, T, V = B.one_electron()
+    X = oracle.orthogonalizer(S)
+    D, _, _ = oracle.density_from_fock(T + V, X, B.nelec // 2)
+    Jo, Ko, (kept, total) = B.fock_jk(D, tau=tau, with_counts=True)
+    assert st["quartets_total"] == total
+    assert st["quartets_kept"] == kept
+    r = ctx.fock_build(_dev(D), want_jk=True)
+    assert np.max(np.abs(r["J"].cpu().numpy() - Jo)) < 1e-11
+    assert np.max(np.abs(r["K"].cpu().numpy() - Ko)) < 1e-11
+
+
+def test_water10_jk_sampled_elements():
+    b, w = synth.workload("water10")
+    ctx = _ctx(b, tau=w["tau"])
+    _, st = ctx.schwarz_screen()
+    B = oracle.Basis(b)
+    S, T, V = B.one_electron()
+    X = oracle.orthogonalizer(S)
+    D, _, _ = oracle.density_from_fock(T + V, X, B.nelec // 2)
+    r = ctx.fock_build(_dev(D), want_jk=True)
+    rng = np.random.default_rng(10)
+    mus = rng.integers(0, B.nbf, 24)
+    nus = rng.integers(0, B.nbf, 24)
+    Je, Ke = B.jk_elements(D, mus, nus, tau=w["tau"])
+    J, K = r["J"].cpu().numpy(), r["K"].cpu().numpy()
+    print("water10 sampled |dJ|, |dK| =", np.max(np.abs(J[mus, nus] - Je)),
+          np.max(np.abs(K[mus, nus] - Ke)))
+    assert np.max(np.abs(J[mus, nus] - Je)) < 1e-10
+    assert np.max(np.abs(K[mus, nus] - Ke)) < 1e-10
+
+
+# ---------------------------------------------------------------------------
+# SCF
+# ---------------------------------------------------------------------------
+
+
+def _golden(name):
+    p = os.path.join(GOLDEN, f"{name}_oracle.json")
+    if not os.path.exists(p):
+        pytest.skip(f"no stored oracle result {p}")
+    return json.load(open(p))
+
+
+def test_scf_h8_chain():
+    g = _golden("h8_chain")
+    b, w = synth.workload("h8_chain")
+    ctx = _ctx(b, tau=w["tau"], conv_rms_dD=w["conv_rms_dD"], conv_dE=w["conv_dE"])
+    r = ctx.scf(verbose=True)
+    assert r["converged"]
+    print("h8 dE vs oracle =", r["E_total"] - g["E_total"])
+    assert abs(r["E_total"] - g["E_total"]) < 1e-8
+    assert abs(r["iterations"] - g["iterations"]) <= 1
+
+
+def test_scf_water_dimer_against_oracle_scf():
+    b = synth.water_cluster(2, 7)
+    ro = oracle.scf(b, conv_rms_dD=1e-9, conv_dE=1e-11)
+    ctx = _ctx(b, conv_rms_dD=1e-9, conv_dE=1e-11)
+    r = ctx.scf()
+    assert r["converged"]
+    assert abs(r["E_total"] - ro["E_total"]) < 1e-8
+    D = r["D"].cpu().numpy()
+    S = ro["S"]
+    P = D / 2
+    assert np.allclose(P @ S @ P, P, atol=1e-7)
+    assert np.trace(D @ S) == pytest.approx(b["nelec"], abs=1e-8)
+
+
+def test_scf_water10():
+    g = _golden("water10")
+    b, w = synth.workload("water10")
+    ctx = _ctx(b, tau=w["tau"], conv_rms_dD=w["conv_rms_dD"], conv_dE=w["conv_dE"])
+    r = ctx.scf(verbose=True)
+    assert r["converged"]
+    print("water10 dE vs oracle =", r["E_total"] - g["E_total"])
+    assert abs(r["E_total"] - g["E_total"]) < 1e-8
+
+
+def test_mixed_precision_water10():
+    b, w = synth.workload("water10")
+    ctx = _ctx(b, tau=w["tau"], tau_fp32=1e-5, conv_rms_dD=w["conv_rms_dD"],
+               conv_dE=w["conv_dE"])
+    _, st = ctx.schwarz_screen()
+    assert st["quartets_fp32"] > 0 and st["quartets_fp64"] > 0
+    r64 = ctx.scf(precision="fp64")
+    rmx = ctx.scf(precision="mixed")
+    print("mixed-fp64:", rmx["E_total"] - r64["E_total"], "unrefined:",
+          rmx["E_total_mixed"] - r64["E_total"])
+    assert abs(rmx["E_total"] - r64["E_total"]) < 1e-6
+
+
+# ---------------------------------------------------------------------------
+# edge cases
+# ---------------------------------------------------------------------------
+
+
+def test_single_function_two_electrons():
+    b = custom_basis([([0, 0, 0], 2.0, [(0, [1.5, 0.4], [0.6, 0.5])])])
+    ro = oracle.scf(b, conv_rms_dD=1e-12)
+    ctx = _ctx(b, conv_rms_dD=1e-12, conv_dE=0.0)
+    r = ctx.scf()
+    assert r["converged"] and abs(r["E_total"] - ro["E_total"]) < 1e-10
+
+
+def test_everything_screened_out_gives_core_fock():
+    b = synth.h_chain(4, 1.4)
+    ctx = _ctx(b)
+    ctx.schwarz_screen(tau=1e6)
+    D = _random_density(ctx.nbf, 3)
+    r = ctx.fock_build(_dev(D), want_jk=True)
+    S, H, X = ctx.one_electron()
+    assert torch.all(r["J"] == 0) and torch.all(r["K"] == 0)
+    assert torch.equal(r["F"], H)
+
+
+def test_diis_off_and_rescreen():
+    b = synth.water_cluster(1, 3)
+    ro = oracle.scf(b, conv_rms_dD=1e-9, conv_dE=1e-11)
+    ctx = _ctx(b, diis_m=0, conv_rms_dD=1e-9, conv_dE=1e-11)
+    r = ctx.scf(max_iter=200)
+    assert r["converged"] and abs(r["E_total"] - ro["E_total"]) < 1e-8
+    ctx.schwarz_screen(tau=1e-12)
+    ctx.schwarz_screen(tau=0.0)
+    r2 = ctx.scf(max_iter=200)
+    assert abs(r2["E_total"] - ro["E_total"]) < 1e-8
+
+
+def test_fock_build_before_screen_is_an_error():
+    b = synth.h_chain(2, 1.4)
+    ctx = _ctx(b)
+    with pytest.raises(_fsim().FsimError, match="screen"):
+        ctx.fock_build(_dev(np.eye(ctx.nbf)))

@@ -1,0 +1,216 @@
+#!/usr/bin/env python
+"""Direct-SCF Fock-build throughput on one MI355X.
+
+One step = one SCF iteration of the hot path through the C ABI: the direct
+Fock build over every Schwarz-kept canonical shell quartet (McMurchie-Davidson
+integrals digested into J and K) followed by the SCF step (DIIS, X^T F X,
+rocSOLVER diagonalisation, new density).  The pair tables and the Schwarz
+screen are built once per geometry, before the timed region, as in any SCF.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload water64]
+
+Prints one JSON line.  `value` is screened quartets per second of the FP64
+steps; the mixed-precision steps are reported beside it.
+"""
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "screened ERI quartets/s + Fock-build s/iter (FP64 vs mixed) at ΔE≤1e-6 Ha"
+FP64_PEAK_TFLOPS = 78.6     # MI355X FP64 vector: 256 CU x 2.4 GHz x 128 flop/clk
+FP32_PEAK_TFLOPS = 157.3    # MI355X FP32 vector (published)
+
+
+def log(*a):
+    print("[bench]", *a, file=sys.stderr, flush=True)
+
+
+def cpu_baseline(basis, w, D, target_s=15.0, seed=0):
+    """Oracle (plain FP64 C, OpenMP) on a bounded random sample of the
+    workload's Schwarz-kept canonical quartets, digested into J/K."""
+    import numpy as np
+    import oracle
+    B = oracle.Basis(basis)
+    Q = B.schwarz()
+    ns = B.nshell
+    iu = np.array([(a, b) for a in range(ns) for b in range(a + 1)], dtype=np.int32)
+    qp = Q[iu[:, 0], iu[:, 1]]
+    rng = np.random.default_rng(seed)
+
+    def draw(n):
+        picks, have = [], 0
+        while have < n:
+            i = rng.integers(0, len(iu), 2_000_000)
+            j = rng.integers(0, len(iu), 2_000_000)
+            lo, hi = np.minimum(i, j), np.maximum(i, j)
+            keep = qp[hi] * qp[lo] >= w["tau"]
+            picks.append(np.concatenate([iu[hi[keep]], iu[lo[keep]]], axis=1))
+            have += int(keep.sum())
+        return np.ascontiguousarray(np.concatenate(picks)[:n])
+
+    Dh = D.cpu().numpy()
+    probe = draw(20_000)
+    t0 = time.time()
+    B.fock_jk_list(Dh, probe)
+    rate = len(probe) / max(time.time() - t0, 1e-6)
+    n = int(min(50_000_000, max(20_000, rate * target_s)))
+    quartets = draw(n)
+    t0 = time.time()
+    B.fock_jk_list(Dh, quartets)
+    t = time.time() - t0
+    return {"value": n / t, "unit": "screened quartets/s", "cores": oracle.num_threads(),
+            "kind": "oracle",
+            "sample": f"{n} uniformly drawn Schwarz-kept canonical quartets of the same "
+                      f"workload, digested into J/K at the core-guess density ({t:.1f} s)"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="water64")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--no-mixed", action="store_true")
+    a = ap.parse_args()
+    if a.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(the sharding design is described in DESIGN.md); run with --gpus 1",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import synth
+    from paper_2510_24968_amd import fsim
+
+    basis, w = synth.workload(a.workload)
+    tau32 = w["tau_fp32"] if w["tau_fp32"] > 0 else 1e-5
+    log(f"workload {a.workload}: {basis['name']}")
+    t0 = time.time()
+    ctx = fsim.Context(basis, tau=w["tau"], tau_fp32=tau32, conv_rms_dD=w["conv_rms_dD"],
+                       conv_dE=w["conv_dE"])
+    torch.cuda.synchronize()
+    t_setup = time.time() - t0
+    t0 = time.time()
+    _, st = ctx.schwarz_screen()
+    t_screen = time.time() - t0
+    log(f"nbf={ctx.nbf} setup {t_setup:.2f}s screen {t_screen:.2f}s kept {st['quartets_kept']}"
+        f" of {st['quartets_total']} (fp32 part {st['quartets_fp32']})")
+
+    def timed_steps(prec):
+        ctx.scf_reset()
+        D = ctx.core_guess()
+        for _ in range(a.warmup):
+            ctx.scf_step(D, prec)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        tw = time.time()
+        e0.record()
+        info = None
+        for k in range(a.steps):
+            info = ctx.scf_step(D, prec)
+            log(f"{prec} step {k + 1}/{a.steps} E={info['E_total']:.10f}")
+        e1.record()
+        torch.cuda.synchronize()
+        wall = time.time() - tw
+        return e0.elapsed_time(e1) / a.steps, wall, info, D
+
+    ms64, wall64, info64, D64 = timed_steps("fp64")
+    res_mixed = None
+    if not a.no_mixed:
+        msmx, wallmx, infomx, Dmx = timed_steps("mixed")
+    # Fock build alone, and the mixed-vs-FP64 energy difference, at one density
+    Dfix = ctx.core_guess()
+    for _ in range(2):
+        ctx.fock_build(Dfix, "fp64", energy=False)
+    fb = {}
+    E = {}
+    for prec in (["fp64"] if a.no_mixed else ["fp64", "mixed"]):
+        times = []
+        for _ in range(max(3, a.steps)):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            ctx.fock_build(Dfix, prec, energy=False)
+            e1.record()
+            torch.cuda.synchronize()
+            times.append(e0.elapsed_time(e1))
+        times.sort()
+        fb[prec] = times[len(times) // 2] / 1e3
+        E[prec] = ctx.fock_build(Dfix, prec)["E_elec"]
+    # per-class kernel times of one FP64 build (HIP events on the build stream)
+    ctx.set_profiling(True)
+    ctx.fock_build(Dfix, "fp64", energy=False)
+    prof = ctx.class_profile()
+    prof_mixed = []
+    if not a.no_mixed:
+        ctx.fock_build(Dfix, "mixed", energy=False)
+        prof_mixed = ctx.class_profile()
+    ctx.set_profiling(False)
+    dom = max(prof, key=lambda r: r["ms"])
+    achieved = dom["flops"] / (dom["ms"] * 1e-3) / 1e12
+    total_flops = sum(r["flops"] for r in prof)
+    total_ms = sum(r["ms"] for r in prof)
+
+    nq = st["quartets_kept"]
+    out = {
+        "metric": METRIC,
+        "value": nq * 1e3 / ms64,
+        "unit": "screened quartets/s",
+        "n_gpus": 1,
+        "steps": a.steps,
+        "warmup": a.warmup,
+        "ms_per_step": ms64,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"{a.workload}: {basis['name']}, {ctx.nbf} Cartesian basis "
+                               f"functions, {ctx.nelec} electrons",
+                   "tau_screen": w["tau"], "tau_fp32": tau32,
+                   "quartets_screened": nq, "quartets_canonical": st["quartets_total"],
+                   "prim_quartets_screened": st["prim_quartets_kept"],
+                   "parallelism": "single GPU"},
+        "fock_build_s": fb,
+        "scf_step_wall_s": wall64 / a.steps,
+        "setup_s": t_setup,
+        "screen_s": t_screen,
+        "model_flops_per_build": {"fp64": st["flops_fp64"],
+                                  "mixed_fp64": st["flops_mixed_fp64"],
+                                  "mixed_fp32": st["flops_mixed_fp32"]},
+        "fock_build_fp64_tflops": total_flops / (total_ms * 1e-3) / 1e12,
+        "roofline": {"bound": "alu", "kernel": f"k_eri {dom['cls']} fp64",
+                     "achieved": achieved, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
+                     "frac": achieved / FP64_PEAK_TFLOPS, "traffic": None,
+                     "launch_ms": dom["ms"], "launch_flops": dom["flops"]},
+        "class_profile": [{"cls": r["cls"], "ms": round(r["ms"], 4),
+                           "quartets": r["quartets"],
+                           "tflops": round(r["flops"] / max(r["ms"], 1e-9) / 1e9, 3)}
+                          for r in sorted(prof, key=lambda r: -r["ms"])],
+    }
+    if not a.no_mixed:
+        out["class_profile_mixed"] = [
+            {"cls": r["cls"] + (" f32" if r["fp32"] else " f64"), "ms": round(r["ms"], 4),
+             "quartets": r["quartets"],
+             "tflops": round(r["flops"] / max(r["ms"], 1e-9) / 1e9, 3)}
+            for r in sorted(prof_mixed, key=lambda r: -r["ms"])]
+        out["mixed"] = {"value": nq * 1e3 / msmx, "ms_per_step": msmx, "dtype": "f64+f32",
+                        "dE_vs_fp64_build_Ha": E["mixed"] - E["fp64"],
+                        "quartets_fp32": st["quartets_fp32"],
+                        "speedup_vs_fp64": ms64 / msmx,
+                        "fock_build_speedup_vs_fp64": fb["fp64"] / fb["mixed"]}
+    if not a.no_cpu_baseline:
+        log("cpu baseline (oracle sample)")
+        out["cpu_baseline"] = cpu_baseline(basis, w, Dfix, a.cpu_seconds)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

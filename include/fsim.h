@@ -168,6 +168,28 @@ fsim_status fsim_scf_step(fsim_ctx *ctx, double *D, fsim_scf_info *info, fsim_pr
 /* Forget the DIIS history and the step counter. */
 fsim_status fsim_scf_reset(fsim_ctx *ctx);
 
+/* Per-launch record of the last profiled Fock build: one entry per quartet
+ * class (bra pair class >= ket pair class; 0..5 = ss ps pp ds dp dd) and
+ * precision that had work.  ms is the kernel's duration measured with HIP
+ * events recorded on the build's stream around that launch. */
+typedef struct {
+    int32_t bra_class, ket_class;
+    int32_t fp32;             /* 1 for the FP32 part of a mixed build */
+    int32_t tiles;            /* wave tiles (one bra pair x up to 64 kets) */
+    int64_t quartets;         /* contracted quartets evaluated */
+    int64_t prim_quartets;    /* primitive quartets */
+    double flops;             /* algorithmic flop model of the launch */
+    double ms;                /* measured kernel time */
+} fsim_class_profile;
+
+/* Enable (1) or disable (0) per-launch timing of subsequent Fock builds. */
+fsim_status fsim_set_profiling(fsim_ctx *ctx, int32_t enable);
+
+/* Copy up to cap records of the last profiled build into out (host);
+ * *count receives the number of records available. */
+fsim_status fsim_get_class_profile(fsim_ctx *ctx, fsim_class_profile *out, int32_t cap,
+                               int32_t *count);
+
 /* Contracted ERI blocks (Eq. twoe-final summed over primitives) for n shell
  * quartets, evaluated by the Fock-build kernels but written out instead of
  * digested.  quartets: host [n*4] shell indices (a, b, c, d) in any order.

@@ -74,6 +74,7 @@ def _load():
     lib.or_fock_jk.argtypes = [ctypes.c_void_p, _dp, ctypes.c_double, _dp, _dp, _dp, _i64p]
     lib.or_jk_elements.argtypes = [ctypes.c_void_p, _dp, ctypes.c_double, _dp, ctypes.c_int,
                                    _ip, _ip, _dp, _dp]
+    lib.or_fock_jk_list.argtypes = [ctypes.c_void_p, _dp, ctypes.c_int64, _ip, _dp, _dp]
     lib.or_num_threads.restype = ctypes.c_int
     lib.or_set_threads.argtypes = [ctypes.c_int]
     _lib = lib
@@ -231,6 +232,16 @@ class Basis:
         _lib.or_jk_elements(self.h, _d(D), float(tau), _d(Q), len(mus), _i(mus), _i(nus),
                             _d(Jo), _d(Ko))
         return Jo, Ko
+
+
+    def fock_jk_list(self, D, quartets):
+        """J, K contributions of an explicit list of canonical shell quartets."""
+        D = np.ascontiguousarray(D, dtype=np.float64)
+        q = np.ascontiguousarray(quartets, dtype=np.int32).reshape(-1, 4)
+        N = self.nbf
+        J, K = np.zeros((N, N)), np.zeros((N, N))
+        _lib.or_fock_jk_list(self.h, _d(D), len(q), _i(q), _d(J), _d(K))
+        return J, K
 
 
 def jk_from_tensor(g, D):

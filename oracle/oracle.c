@@ -560,6 +560,65 @@ void or_fock_jk(const or_basis *b, const double *D, double tau, const double *Q,
     free(Kh);
 }
 
+/* J and K contributions (already symmetrised) of an explicit list of
+ * canonical shell quartets q[4*i..4*i+3] = (sa, sb, sc, sd) with sa >= sb,
+ * sc >= sd and pair(sa,sb) >= pair(sc,sd), digested exactly as in
+ * or_fock_jk.  Used to time the oracle on a bounded sample of a workload. */
+void or_fock_jk_list(const or_basis *b, const double *D, int64_t n, const int *q, double *J,
+                     double *K)
+{
+    int N = b->nbf;
+    double *Jh = (double *)calloc((size_t)N * N, sizeof(double));
+    double *Kh = (double *)calloc((size_t)N * N, sizeof(double));
+#pragma omp parallel
+    {
+        double *Jt = (double *)calloc((size_t)N * N, sizeof(double));
+        double *Kt = (double *)calloc((size_t)N * N, sizeof(double));
+        double blk[6 * 6 * 6 * 6];
+#pragma omp for schedule(dynamic, 16)
+        for (int64_t e = 0; e < n; e++) {
+            int sa = q[4 * e], sb = q[4 * e + 1], sc = q[4 * e + 2], sd = q[4 * e + 3];
+            or_eri_block(b, sa, sb, sc, sd, blk);
+            double f = 1.0;
+            if (sa == sb) f *= 0.5;
+            if (sc == sd) f *= 0.5;
+            if (sa == sc && sb == sd) f *= 0.5;
+            int nn[4] = {ncart(b->sh_l[sa]), ncart(b->sh_l[sb]), ncart(b->sh_l[sc]),
+                         ncart(b->sh_l[sd])};
+            for (int i = 0; i < nn[0]; i++)
+                for (int j = 0; j < nn[1]; j++)
+                    for (int k = 0; k < nn[2]; k++)
+                        for (int m = 0; m < nn[3]; m++) {
+                            size_t I = b->sh_bf0[sa] + i, Jx = b->sh_bf0[sb] + j,
+                                   Kx = b->sh_bf0[sc] + k, Lx = b->sh_bf0[sd] + m;
+                            double v = f * blk[((i * nn[1] + j) * nn[2] + k) * nn[3] + m];
+                            Jt[I * N + Jx] += 2.0 * v * D[Kx * N + Lx];
+                            Jt[Kx * N + Lx] += 2.0 * v * D[I * N + Jx];
+                            Kt[I * N + Kx] += v * D[Jx * N + Lx];
+                            Kt[Jx * N + Kx] += v * D[I * N + Lx];
+                            Kt[I * N + Lx] += v * D[Jx * N + Kx];
+                            Kt[Jx * N + Lx] += v * D[I * N + Kx];
+                        }
+        }
+#pragma omp critical
+        {
+            for (size_t x = 0; x < (size_t)N * N; x++) {
+                Jh[x] += Jt[x];
+                Kh[x] += Kt[x];
+            }
+        }
+        free(Jt);
+        free(Kt);
+    }
+    for (int i = 0; i < N; i++)
+        for (int j = 0; j < N; j++) {
+            J[i * N + j] = Jh[i * N + j] + Jh[j * N + i];
+            K[i * N + j] = Kh[i * N + j] + Kh[j * N + i];
+        }
+    free(Jh);
+    free(Kh);
+}
+
 /* Single elements J_mn = sum_ls (mn|ls) D_ls and K_mn = sum_ls (ml|ns) D_ls
  * straight from their definition (every ordered shell pair on the summed
  * side), keeping a quartet when its Schwarz bound is >= tau.  For sampled

@@ -50,8 +50,13 @@ namespace {
 
 // Quartet work lists of one class pair: FP64-mode list, and the two parts
 // of the mixed-mode split.
+struct ListStats {
+    int64_t nq = 0, npq = 0;
+    double flops = 0.0;
+};
 struct ClassLists {
     TileList all64, mix64, mix32;
+    ListStats s64, sm64, sm32;
 };
 
 struct DevPool {
@@ -110,6 +115,11 @@ struct fsim_ctx {
     double *eig = nullptr, *ework = nullptr, *scal = nullptr;
     int *dinfo = nullptr;
     rocblas_handle blas = nullptr;
+
+    // per-launch profiling
+    bool profiling = false;
+    std::vector<hipEvent_t> ev;
+    std::vector<fsim_class_profile> prof;
 
     // DIIS and step state
     std::vector<double *> dF, dE;
@@ -424,6 +434,7 @@ extern "C" fsim_status fsim_ctx_destroy(fsim_ctx *c) {
     if (!c) return FSIM_OK;
     hipDeviceSynchronize();
     if (c->blas) rocblas_destroy_handle(c->blas);
+    for (auto &e : c->ev) hipEventDestroy(e);
     c->screen_pool.clear();
     c->pool.clear();
     delete c;
@@ -764,15 +775,29 @@ extern "C" fsim_status fsim_schwarz_screen(fsim_ctx *c, double tau, double tau32
             }
             std::vector<long long> kpre(kk.size() + 1, 0);
             for (size_t j = 0; j < kk.size(); ++j) kpre[j + 1] = kpre[j] + kk[j];
+            cl.s64 = cl.sm64 = cl.sm32 = ListStats{};
             for (size_t t = 0; t < b64.size(); ++t) {
                 const long long pq = (long long)kb[b64[t]] * (kpre[hi64[t]] - kpre[lo64[t]]);
                 S.prim_quartets_kept += pq;
                 S.flops_fp64 += fpq * pq;
+                cl.s64.npq += pq;
+                cl.s64.flops += fpq * pq;
             }
-            for (size_t t = 0; t < bm64.size(); ++t)
-                S.flops_mixed_fp64 += fpq * (double)kb[bm64[t]] * (kpre[him64[t]] - kpre[lom64[t]]);
-            for (size_t t = 0; t < bm32.size(); ++t)
-                S.flops_mixed_fp32 += fpq * (double)kb[bm32[t]] * (kpre[him32[t]] - kpre[lom32[t]]);
+            cl.s64.nq = cl.all64.nquartet;
+            for (size_t t = 0; t < bm64.size(); ++t) {
+                const long long pq = (long long)kb[bm64[t]] * (kpre[him64[t]] - kpre[lom64[t]]);
+                S.flops_mixed_fp64 += fpq * pq;
+                cl.sm64.npq += pq;
+                cl.sm64.flops += fpq * pq;
+            }
+            cl.sm64.nq = cl.mix64.nquartet;
+            for (size_t t = 0; t < bm32.size(); ++t) {
+                const long long pq = (long long)kb[bm32[t]] * (kpre[him32[t]] - kpre[lom32[t]]);
+                S.flops_mixed_fp32 += fpq * pq;
+                cl.sm32.npq += pq;
+                cl.sm32.flops += fpq * pq;
+            }
+            cl.sm32.nq = cl.mix32.nquartet;
         }
     if (tau32 <= 0) {
         S.quartets_fp64 = S.quartets_kept;
@@ -801,6 +826,12 @@ static fsim_status fock_build(fsim_ctx *c, const double *D, double *F, double *J
     HIPCHK(fill(c->Jh, N2, 0.0, s));
     HIPCHK(fill(c->Kh, N2, 0.0, s));
     const bool mixed = prec == FSIM_MIXED && c->tau32 > 0;
+    std::vector<fsim_class_profile> prof;
+    int nev = 0;
+    if (c->profiling && c->ev.empty()) {
+        c->ev.resize(2 * 2 * NPCLASS * NPCLASS);
+        for (auto &e : c->ev) HIPCHK(hipEventCreate(&e));
+    }
     // heaviest classes (highest L) first
     for (int X = NPCLASS - 1; X >= 0; --X)
         for (int Y = X; Y >= 0; --Y) {
@@ -808,6 +839,19 @@ static fsim_status fock_build(fsim_ctx *c, const double *D, double *F, double *J
             for (int part = 0; part < (mixed ? 2 : 1); ++part) {
                 const TileList &tl = mixed ? (part == 0 ? cl.mix64 : cl.mix32) : cl.all64;
                 if (tl.ntile == 0) continue;
+                if (c->profiling) {
+                    const ListStats &ls = mixed ? (part == 0 ? cl.sm64 : cl.sm32) : cl.s64;
+                    fsim_class_profile pr{};
+                    pr.bra_class = X;
+                    pr.ket_class = Y;
+                    pr.fp32 = mixed && part == 1;
+                    pr.tiles = tl.ntile;
+                    pr.quartets = ls.nq;
+                    pr.prim_quartets = ls.npq;
+                    pr.flops = ls.flops;
+                    prof.push_back(pr);
+                    HIPCHK(hipEventRecord(c->ev[nev++], s));
+                }
                 EriArgs a{};
                 a.bra = c->kept[X];
                 a.ket = c->kept[Y];
@@ -819,9 +863,19 @@ static fsim_status fock_build(fsim_ctx *c, const double *D, double *F, double *J
                 a.nbf = N;
                 a.boys = c->boys;
                 HIPCHK(launch_eri(X, Y, mixed && part == 1, false, a, s));
+                if (c->profiling) HIPCHK(hipEventRecord(c->ev[nev++], s));
             }
         }
     HIPCHK(assemble_fock(N, c->Jh, c->Kh, c->H, F, J, K, s));
+    if (c->profiling) {
+        HIPCHK(hipStreamSynchronize(s));
+        for (size_t k = 0; k < prof.size(); ++k) {
+            float ms = 0.f;
+            HIPCHK(hipEventElapsedTime(&ms, c->ev[2 * k], c->ev[2 * k + 1]));
+            prof[k].ms = ms;
+        }
+        c->prof = prof;
+    }
     if (E_elec) {
         if (!F) return fail(FSIM_EINVAL, "E_elec needs F");
         HIPCHK(fill(c->scal, 1, 0.0, s));
@@ -839,6 +893,21 @@ extern "C" fsim_status fsim_fock_build(fsim_ctx *c, const double *D, double *F, 
     double *Fo = F;
     if (!Fo && E_elec) Fo = c->F;
     return fock_build(c, D, Fo, J, K, E_elec, prec, s);
+}
+
+extern "C" fsim_status fsim_set_profiling(fsim_ctx *c, int32_t enable) {
+    if (!c) return fail(FSIM_EINVAL, "ctx is NULL");
+    c->profiling = enable != 0;
+    return FSIM_OK;
+}
+
+extern "C" fsim_status fsim_get_class_profile(fsim_ctx *c, fsim_class_profile *out, int32_t cap,
+                                          int32_t *count) {
+    if (!c || !count) return fail(FSIM_EINVAL, "NULL argument");
+    *count = (int32_t)c->prof.size();
+    if (out)
+        for (int32_t k = 0; k < cap && k < *count; ++k) out[k] = c->prof[k];
+    return FSIM_OK;
 }
 
 extern "C" fsim_status fsim_core_guess(fsim_ctx *c, double *D, void *stream) {

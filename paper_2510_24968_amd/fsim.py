@@ -56,6 +56,16 @@ class _ScfInfo(ctypes.Structure):
                 ("pad", ctypes.c_int32)]
 
 
+class _ClassProfile(ctypes.Structure):
+    _fields_ = [("bra_class", ctypes.c_int32), ("ket_class", ctypes.c_int32),
+                ("fp32", ctypes.c_int32), ("tiles", ctypes.c_int32),
+                ("quartets", ctypes.c_int64), ("prim_quartets", ctypes.c_int64),
+                ("flops", ctypes.c_double), ("ms", ctypes.c_double)]
+
+
+PAIR_CLASS = ("ss", "ps", "pp", "ds", "dp", "dd")
+
+
 def _struct_dict(s):
     return {name: getattr(s, name) for name, _ in s._fields_ if name != "pad"}
 
@@ -84,6 +94,8 @@ def lib():
         "fsim_scf_step": [vp, vp, ctypes.POINTER(_ScfInfo), ctypes.c_int, vp],
         "fsim_scf_reset": [vp],
         "fsim_eri_quartets": [vp, i64, vp, vp, vp, ctypes.c_int, vp],
+        "fsim_set_profiling": [vp, i32],
+        "fsim_get_class_profile": [vp, vp, i32, ctypes.POINTER(i32)],
     }
     for name, args in sigs.items():
         fn = getattr(L, name)
@@ -204,6 +216,22 @@ class Context:
         _check(lib().fsim_scf_step(self.h, _ptr(D), ctypes.byref(info), _PREC[precision],
                                    _stream()))
         return _struct_dict(info)
+
+    def set_profiling(self, enable=True):
+        _check(lib().fsim_set_profiling(self.h, 1 if enable else 0))
+
+    def class_profile(self):
+        """Per-launch records of the last profiled Fock build."""
+        n = ctypes.c_int32()
+        _check(lib().fsim_get_class_profile(self.h, None, 0, ctypes.byref(n)))
+        arr = (_ClassProfile * max(1, n.value))()
+        _check(lib().fsim_get_class_profile(self.h, arr, n.value, ctypes.byref(n)))
+        out = []
+        for k in range(n.value):
+            d = _struct_dict(arr[k])
+            d["cls"] = f"({PAIR_CLASS[d['bra_class']]}|{PAIR_CLASS[d['ket_class']]})"
+            out.append(d)
+        return out
 
     def eri_quartets(self, quartets, precision="fp64"):
         """Contracted Cartesian blocks (numpy) for an (n, 4) array of shell indices."""

@@ -19,10 +19,11 @@ LIB = os.path.join(HERE, "libfsim.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 
-SOURCES = [
-    "setup.hip", "linalg.hip", "api.cpp",
-    "eri_b0.hip", "eri_b1.hip", "eri_b2.hip", "eri_b3.hip", "eri_b4.hip", "eri_b5.hip",
-]
+_PC = ("ss", "ps", "pp", "ds", "dp", "dd")
+ERI_SOURCES = [f"eri_{_PC[b]}{_PC[k]}_{p}.hip" for b in range(6) for k in range(b + 1)
+               for p in ("f64", "f32")]
+# slowest (highest angular momentum) first so the pool stays busy
+SOURCES = ERI_SOURCES[::-1] + ["eri_dispatch.hip", "setup.hip", "linalg.hip", "api.cpp"]
 
 FLAGS = [
     f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC",

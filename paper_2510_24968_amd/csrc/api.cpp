@@ -177,19 +177,6 @@ static fsim_status build_table(fsim_ctx *c, DevPool &pool, PairTable &t, int pc,
     return FSIM_OK;
 }
 
-static hipError_t launch_eri(int bra_pc, int ket_pc, bool fp32, bool store, const EriArgs &a,
-                             hipStream_t s) {
-    switch (bra_pc) {
-        case 0: return launch_eri_bra0(ket_pc, fp32, store, a, s);
-        case 1: return launch_eri_bra1(ket_pc, fp32, store, a, s);
-        case 2: return launch_eri_bra2(ket_pc, fp32, store, a, s);
-        case 3: return launch_eri_bra3(ket_pc, fp32, store, a, s);
-        case 4: return launch_eri_bra4(ket_pc, fp32, store, a, s);
-        case 5: return launch_eri_bra5(ket_pc, fp32, store, a, s);
-        default: return hipErrorInvalidValue;
-    }
-}
-
 // Column-major GEMM C = op(A) op(B) (all N x N here except the density step).
 static fsim_status gemm(rocblas_handle h, bool ta, bool tb, int m, int n, int k, double alpha,
                         const double *A, int lda, const double *B, int ldb, double beta,

@@ -1,0 +1,10 @@
+// (dd|dd) class kernels, FP32 arithmetic.
+#include "eri_kernels.h"
+
+namespace fsim {
+
+hipError_t launch_eri_dddd_f32(bool store, const EriArgs &a, hipStream_t s) {
+    return launch_class<2, 2, 2, 2, float>(store, a, s);
+}
+
+}  // namespace fsim

@@ -1,0 +1,10 @@
+// (dd|dp) class kernels, FP64 arithmetic.
+#include "eri_kernels.h"
+
+namespace fsim {
+
+hipError_t launch_eri_dddp_f64(bool store, const EriArgs &a, hipStream_t s) {
+    return launch_class<2, 2, 2, 1, double>(store, a, s);
+}
+
+}  // namespace fsim

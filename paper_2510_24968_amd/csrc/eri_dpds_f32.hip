@@ -1,0 +1,10 @@
+// (dp|ds) class kernels, FP32 arithmetic.
+#include "eri_kernels.h"
+
+namespace fsim {
+
+hipError_t launch_eri_dpds_f32(bool store, const EriArgs &a, hipStream_t s) {
+    return launch_class<2, 1, 2, 0, float>(store, a, s);
+}
+
+}  // namespace fsim

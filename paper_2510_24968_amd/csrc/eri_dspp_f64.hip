@@ -1,0 +1,10 @@
+// (ds|pp) class kernels, FP64 arithmetic.
+#include "eri_kernels.h"
+
+namespace fsim {
+
+hipError_t launch_eri_dspp_f64(bool store, const EriArgs &a, hipStream_t s) {
+    return launch_class<2, 0, 1, 1, double>(store, a, s);
+}
+
+}  // namespace fsim

@@ -46,6 +46,13 @@ __device__ __forceinline__ const double *etab<double>(const PairTable &t) { retu
 template <>
 __device__ __forceinline__ const float *etab<float>(const PairTable &t) { return t.Ef; }
 
+// Wave-uniform read of a table that no kernel writes while it runs, through
+// the constant address space so that it becomes a scalar (SMEM) load.
+template <typename T>
+__device__ __forceinline__ T ldu(const T *p) {
+    return *(const __attribute__((address_space(4))) T *)p;
+}
+
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
@@ -106,13 +113,42 @@ __device__ __forceinline__ int tile_bra(const TileList &tl, int tile) {
 // time.  A wave owns a tile (one bra pair, up to 64 consecutive kets), so the
 // bra's exponents, centre and Hermite tensor are wave-uniform (scalar loads)
 // and the ket tables are read with unit stride across lanes.
+//
+// The block (ab|cd) is produced in chunks of CA bra components a and CC ket
+// components c, so that at most CA*NB x CC*ND values stay live in registers;
+// each chunk re-evaluates the Boys function and R^0 (cheap next to the
+// contraction) and is digested as soon as it is complete.
 // ===========================================================================
-template <int LA, int LB, int LC, int LD, typename T, bool STORE>
+__host__ __device__ constexpr int cmin(int a, int b) { return a < b ? a : b; }
+
+// chunk sizes: halve the ket, then the bra component range until the live
+// block is at most `limit` values
+__host__ __device__ constexpr int chunk_c(int la, int lb, int lc, int ld, int limit) {
+    int ca = ncart(la), cc = ncart(lc);
+    while (ca * ncart(lb) * cc * ncart(ld) > limit) {
+        if (cc > 1) cc = (cc + 1) / 2;
+        else if (ca > 1) ca = (ca + 1) / 2;
+        else break;
+    }
+    return cc;
+}
+__host__ __device__ constexpr int chunk_a(int la, int lb, int lc, int ld, int limit) {
+    int ca = ncart(la), cc = ncart(lc);
+    while (ca * ncart(lb) * cc * ncart(ld) > limit) {
+        if (cc > 1) cc = (cc + 1) / 2;
+        else if (ca > 1) ca = (ca + 1) / 2;
+        else break;
+    }
+    return ca;
+}
+
+template <int LA, int LB, int LC, int LD, typename T, bool STORE, int CA, int CC>
 __global__ __launch_bounds__(256) void k_eri_lane(EriArgs a) {
     constexpr int L = LA + LB + LC + LD, LAB = LA + LB;
     constexpr int NA = ncart(LA), NB = ncart(LB), NC = ncart(LC), ND = ncart(LD);
-    constexpr int NAB = NA * NB, NCD = NC * ND, NHAB = nherm(LAB), NH = nherm(L);
+    constexpr int NHAB = nherm(LAB), NH = nherm(L);
     constexpr int NEB = n_entries(LA, LB), NEK = n_entries(LC, LD);
+    constexpr int NCHA = (NA + CA - 1) / CA, NCHC = (NC + CC - 1) / CC;
     __shared__ double tab[BOYS_LDS];
     boys_stage(tab, a.boys, L);
     __syncthreads();
@@ -122,6 +158,8 @@ __global__ __launch_bounds__(256) void k_eri_lane(EriArgs a) {
     const T *__restrict__ Eb = etab<T>(a.bra);
     const T *__restrict__ Ek = etab<T>(a.ket);
     const size_t nb = a.bra.n, nk = a.ket.n;
+    const int N = a.nbf;
+    const double *__restrict__ D = a.D;
 
     for (int tile0 = blockIdx.x * wpb + (threadIdx.x >> 6); tile0 < ntile;
          tile0 += gridDim.x * wpb) {
@@ -141,198 +179,225 @@ __global__ __launch_bounds__(256) void k_eri_lane(EriArgs a) {
             active = ket < a.tl.ket_hi[b];
             if (!active) ket = k0;
         }
-
-        T out[NAB][NCD];
-#pragma unroll
-        for (int x = 0; x < NAB; ++x)
-#pragma unroll
-            for (int y = 0; y < NCD; ++y) out[x][y] = T(0);
-
         const int nbp = __builtin_amdgcn_readfirstlane(a.bra.nprim[bra]);
         const int nkp = active ? a.ket.nprim[ket] : 0;
-        for (int i = 0; i < nbp; ++i) {
-            const double p = a.bra.p[i * nb + bra];
-            const double Px = a.bra.P[(i * 3 + 0) * nb + bra];
-            const double Py = a.bra.P[(i * 3 + 1) * nb + bra];
-            const double Pz = a.bra.P[(i * 3 + 2) * nb + bra];
-            const T *__restrict__ eb = Eb + (size_t)i * NEB * nb + bra;
-            for (int j = 0; j < nkp; ++j) {
-                const double q = a.ket.p[j * nk + ket];
-                const double X = Px - a.ket.P[(j * 3 + 0) * nk + ket];
-                const double Y = Py - a.ket.P[(j * 3 + 1) * nk + ket];
-                const double Z = Pz - a.ket.P[(j * 3 + 2) * nk + ket];
-                const double pq = p + q, alpha = p * q / pq;
-                double F[L + 1];
-                boys_eval<L>(alpha * (X * X + Y * Y + Z * Z), tab, F);
-                T src[L + 1];
-                double m = 1.0 / sqrt(pq);
-#pragma unroll
-                for (int n = 0; n <= L; ++n) {
-                    src[n] = T(F[n] * m);
-                    m *= -2.0 * alpha;
-                }
-                T r[NH];
-                hermite_r<L, T>(src, T(X), T(Y), T(Z), r);
-                const T *__restrict__ ek = Ek + (size_t)j * NEK * nk + ket;
-                static_for<NCD>([&](auto cd_) {
-                    constexpr int cd = decltype(cd_)::value;
-                    constexpr int bx = box_dim(LC, LD, cd, 0), by = box_dim(LC, LD, cd, 1),
-                                  bz = box_dim(LC, LD, cd, 2);
-                    constexpr int eo = box_off(LC, LD, cd);
-                    T w[NHAB];
-#pragma unroll
-                    for (int h = 0; h < NHAB; ++h) w[h] = T(0);
-                    static_for<bx + 1>([&](auto ta_) {
-                        constexpr int ta = decltype(ta_)::value;
-                        static_for<by + 1>([&](auto nu_) {
-                            constexpr int nu = decltype(nu_)::value;
-                            static_for<bz + 1>([&](auto ph_) {
-                                constexpr int ph = decltype(ph_)::value;
-                                constexpr int e = eo + (ta * (by + 1) + nu) * (bz + 1) + ph;
-                                T ev = ek[(size_t)e * nk];
-                                if constexpr ((ta + nu + ph) & 1) ev = -ev;
-                                static_for<NHAB>([&](auto h_) {
-                                    constexpr int h = decltype(h_)::value;
-                                    constexpr int ri = hidx(hidx_t(h) + ta, hidx_u(h) + nu,
-                                                            hidx_v(h) + ph);
-                                    w[h] = fma(ev, r[ri], w[h]);
-                                });
-                            });
-                        });
-                    });
-                    static_for<NAB>([&](auto ab_) {
-                        constexpr int ab = decltype(ab_)::value;
-                        constexpr int ax = box_dim(LA, LB, ab, 0), ay = box_dim(LA, LB, ab, 1),
-                                      az = box_dim(LA, LB, ab, 2);
-                        constexpr int ao = box_off(LA, LB, ab);
-                        T acc = out[ab][cd];
-                        static_for<ax + 1>([&](auto t_) {
-                            constexpr int t = decltype(t_)::value;
-                            static_for<ay + 1>([&](auto u_) {
-                                constexpr int u = decltype(u_)::value;
-                                static_for<az + 1>([&](auto v_) {
-                                    constexpr int v = decltype(v_)::value;
-                                    constexpr int e = ao + (t * (ay + 1) + u) * (az + 1) + v;
-                                    acc = fma(eb[(size_t)e * nb], w[hidx(t, u, v)], acc);
-                                });
-                            });
-                        });
-                        out[ab][cd] = acc;
-                    });
-                });
-            }
-        }
-
+        int f1 = 0, f2 = 0, f3 = 0, f4 = 0;
+        double fac = 0.0;
+        long long soff = 0;
+        int st0 = 0, st1 = 0, st2 = 0, st3 = 0;
         if constexpr (STORE) {
             if (active) {
                 const size_t q = (size_t)tile * 64 + lane;
-                const long long off = a.st_off[q];
-                const int s0 = a.st_stride[q * 4 + 0], s1 = a.st_stride[q * 4 + 1],
-                          s2 = a.st_stride[q * 4 + 2], s3 = a.st_stride[q * 4 + 3];
-#pragma unroll
-                for (int ia = 0; ia < NA; ++ia)
-#pragma unroll
-                    for (int ib = 0; ib < NB; ++ib)
-#pragma unroll
-                        for (int ic = 0; ic < NC; ++ic)
-#pragma unroll
-                            for (int id = 0; id < ND; ++id)
-                                a.out[off + ia * s0 + ib * s1 + ic * s2 + id * s3] =
-                                    (double)out[ia * NB + ib][ic * ND + id];
+                soff = a.st_off[q];
+                st0 = a.st_stride[q * 4 + 0];
+                st1 = a.st_stride[q * 4 + 1];
+                st2 = a.st_stride[q * 4 + 2];
+                st3 = a.st_stride[q * 4 + 3];
             }
         } else {
-            const int N = a.nbf;
-            const int f1 = __builtin_amdgcn_readfirstlane(a.bra.bf1[bra]);
-            const int f2 = __builtin_amdgcn_readfirstlane(a.bra.bf2[bra]);
-            const int f3 = a.ket.bf1[ket], f4 = a.ket.bf2[ket];
-            double fac = active ? 1.0 : 0.0;
+            f1 = __builtin_amdgcn_readfirstlane(a.bra.bf1[bra]);
+            f2 = __builtin_amdgcn_readfirstlane(a.bra.bf2[bra]);
+            f3 = a.ket.bf1[ket];
+            f4 = a.ket.bf2[ket];
+            fac = active ? 1.0 : 0.0;
             if (a.bra.sh1[bra] == a.bra.sh2[bra]) fac *= 0.5;
             if (a.ket.sh1[ket] == a.ket.sh2[ket]) fac *= 0.5;
             if (a.same_class && ket == bra) fac *= 0.5;
-            const double *__restrict__ D = a.D;
-            // J'_ab: pre-reduced over the wave, one atomic per component
+        }
+
+        static_for<NCHA * NCHC>([&](auto ch_) {
+            constexpr int ch = decltype(ch_)::value;
+            constexpr int A0 = (ch / NCHC) * CA, A1 = cmin(A0 + CA, NA);
+            constexpr int C0 = (ch % NCHC) * CC, C1 = cmin(C0 + CC, NC);
+            constexpr int NAc = A1 - A0, NCc = C1 - C0;
+            constexpr int NABc = NAc * NB, NCDc = NCc * ND;
+            T out[NABc][NCDc];
 #pragma unroll
-            for (int ia = 0; ia < NA; ++ia)
+            for (int x = 0; x < NABc; ++x)
 #pragma unroll
-                for (int ib = 0; ib < NB; ++ib) {
-                    double s = 0.0;
+                for (int y = 0; y < NCDc; ++y) out[x][y] = T(0);
+
+            for (int i = 0; i < nbp; ++i) {
+                const double p = ldu(a.bra.p + i * nb + bra);
+                const double Px = ldu(a.bra.P + (i * 3 + 0) * nb + bra);
+                const double Py = ldu(a.bra.P + (i * 3 + 1) * nb + bra);
+                const double Pz = ldu(a.bra.P + (i * 3 + 2) * nb + bra);
+                const T *__restrict__ eb = Eb + (size_t)i * NEB * nb + bra;
+                for (int j = 0; j < nkp; ++j) {
+                    // keep the bra tensor in scalar loads inside the loop
+                    // instead of letting it be hoisted into vector registers
+                    __asm__ __volatile__("" ::: "memory");
+                    const double q = a.ket.p[j * nk + ket];
+                    const double X = Px - a.ket.P[(j * 3 + 0) * nk + ket];
+                    const double Y = Py - a.ket.P[(j * 3 + 1) * nk + ket];
+                    const double Z = Pz - a.ket.P[(j * 3 + 2) * nk + ket];
+                    const double pq = p + q, alpha = p * q / pq;
+                    double F[L + 1];
+                    boys_eval<L>(alpha * (X * X + Y * Y + Z * Z), tab, F);
+                    T src[L + 1];
+                    double m = 1.0 / sqrt(pq);
 #pragma unroll
-                    for (int ic = 0; ic < NC; ++ic)
+                    for (int n = 0; n <= L; ++n) {
+                        src[n] = T(F[n] * m);
+                        m *= -2.0 * alpha;
+                    }
+                    T r[NH];
+                    hermite_r<L, T>(src, T(X), T(Y), T(Z), r);
+                    const T *__restrict__ ek = Ek + (size_t)j * NEK * nk + ket;
+                    static_for<NCDc>([&](auto cdl_) {
+                        constexpr int cdl = decltype(cdl_)::value;
+                        constexpr int cd = (C0 + cdl / ND) * ND + cdl % ND;
+                        constexpr int bx = box_dim(LC, LD, cd, 0), by = box_dim(LC, LD, cd, 1),
+                                      bz = box_dim(LC, LD, cd, 2);
+                        constexpr int eo = box_off(LC, LD, cd);
+                        T w[NHAB];
 #pragma unroll
-                        for (int id = 0; id < ND; ++id)
-                            s += (double)out[ia * NB + ib][ic * ND + id] *
-                                 D[(size_t)(f3 + ic) * N + f4 + id];
-                    s = wave_sum(2.0 * fac * s);
-                    if (lane == 0) atomicAdd(&a.Jh[(size_t)(f1 + ia) * N + f2 + ib], s);
+                        for (int h = 0; h < NHAB; ++h) w[h] = T(0);
+                        static_for<bx + 1>([&](auto ta_) {
+                            constexpr int ta = decltype(ta_)::value;
+                            static_for<by + 1>([&](auto nu_) {
+                                constexpr int nu = decltype(nu_)::value;
+                                static_for<bz + 1>([&](auto ph_) {
+                                    constexpr int ph = decltype(ph_)::value;
+                                    constexpr int e = eo + (ta * (by + 1) + nu) * (bz + 1) + ph;
+                                    T ev = ek[(size_t)e * nk];
+                                    if constexpr ((ta + nu + ph) & 1) ev = -ev;
+                                    static_for<NHAB>([&](auto h_) {
+                                        constexpr int h = decltype(h_)::value;
+                                        constexpr int ri = hidx(hidx_t(h) + ta, hidx_u(h) + nu,
+                                                                hidx_v(h) + ph);
+                                        w[h] = fma(ev, r[ri], w[h]);
+                                    });
+                                });
+                            });
+                        });
+                        static_for<NABc>([&](auto abl_) {
+                            constexpr int abl = decltype(abl_)::value;
+                            constexpr int ab = (A0 + abl / NB) * NB + abl % NB;
+                            constexpr int ax = box_dim(LA, LB, ab, 0), ay = box_dim(LA, LB, ab, 1),
+                                          az = box_dim(LA, LB, ab, 2);
+                            constexpr int ao = box_off(LA, LB, ab);
+                            T acc = out[abl][cdl];
+                            static_for<ax + 1>([&](auto t_) {
+                                constexpr int t = decltype(t_)::value;
+                                static_for<ay + 1>([&](auto u_) {
+                                    constexpr int u = decltype(u_)::value;
+                                    static_for<az + 1>([&](auto v_) {
+                                        constexpr int v = decltype(v_)::value;
+                                        constexpr int e = ao + (t * (ay + 1) + u) * (az + 1) + v;
+                                        acc = fma(ldu(eb + (size_t)e * nb), w[hidx(t, u, v)], acc);
+                                    });
+                                });
+                            });
+                            out[abl][cdl] = acc;
+                        });
+                    });
                 }
-            if (active) {
+            }
+
+            if constexpr (STORE) {
+                if (active) {
 #pragma unroll
-                for (int ic = 0; ic < NC; ++ic)
+                    for (int ia = A0; ia < A1; ++ia)
 #pragma unroll
-                    for (int id = 0; id < ND; ++id) {
-                        double s = 0.0;
+                        for (int ib = 0; ib < NB; ++ib)
 #pragma unroll
-                        for (int ia = 0; ia < NA; ++ia)
+                            for (int ic = C0; ic < C1; ++ic)
+#pragma unroll
+                                for (int id = 0; id < ND; ++id)
+                                    a.out[soff + ia * st0 + ib * st1 + ic * st2 + id * st3] =
+                                        (double)out[(ia - A0) * NB + ib][(ic - C0) * ND + id];
+                }
+            } else {
+                // J'_ab (partial over this chunk's c): pre-reduced over the wave
+#pragma unroll
+                for (int ia = A0; ia < A1; ++ia)
+#pragma unroll
+                    for (int ib = 0; ib < NB; ++ib) {
+                        double sum = 0.0;
+#pragma unroll
+                        for (int ic = C0; ic < C1; ++ic)
+#pragma unroll
+                            for (int id = 0; id < ND; ++id)
+                                sum += (double)out[(ia - A0) * NB + ib][(ic - C0) * ND + id] *
+                                       D[(size_t)(f3 + ic) * N + f4 + id];
+                        sum = wave_sum(2.0 * fac * sum);
+                        if (lane == 0) atomicAdd(&a.Jh[(size_t)(f1 + ia) * N + f2 + ib], sum);
+                    }
+                if (active) {
+                    // J'_cd (partial over this chunk's a)
+#pragma unroll
+                    for (int ic = C0; ic < C1; ++ic)
+#pragma unroll
+                        for (int id = 0; id < ND; ++id) {
+                            double sum = 0.0;
+#pragma unroll
+                            for (int ia = A0; ia < A1; ++ia)
+#pragma unroll
+                                for (int ib = 0; ib < NB; ++ib)
+                                    sum += (double)out[(ia - A0) * NB + ib][(ic - C0) * ND + id] *
+                                           D[(size_t)(f1 + ia) * N + f2 + ib];
+                            atomicAdd(&a.Jh[(size_t)(f3 + ic) * N + f4 + id], 2.0 * fac * sum);
+                        }
+                    // K'_ac (complete)
+#pragma unroll
+                    for (int ia = A0; ia < A1; ++ia)
+#pragma unroll
+                        for (int ic = C0; ic < C1; ++ic) {
+                            double sum = 0.0;
 #pragma unroll
                             for (int ib = 0; ib < NB; ++ib)
-                                s += (double)out[ia * NB + ib][ic * ND + id] *
-                                     D[(size_t)(f1 + ia) * N + f2 + ib];
-                        atomicAdd(&a.Jh[(size_t)(f3 + ic) * N + f4 + id], 2.0 * fac * s);
-                    }
 #pragma unroll
-                for (int ia = 0; ia < NA; ++ia)
+                                for (int id = 0; id < ND; ++id)
+                                    sum += (double)out[(ia - A0) * NB + ib][(ic - C0) * ND + id] *
+                                           D[(size_t)(f2 + ib) * N + f4 + id];
+                            atomicAdd(&a.Kh[(size_t)(f1 + ia) * N + f3 + ic], fac * sum);
+                        }
+                    // K'_bc (partial over a)
 #pragma unroll
-                    for (int ic = 0; ic < NC; ++ic) {
-                        double s = 0.0;
+                    for (int ib = 0; ib < NB; ++ib)
 #pragma unroll
-                        for (int ib = 0; ib < NB; ++ib)
+                        for (int ic = C0; ic < C1; ++ic) {
+                            double sum = 0.0;
 #pragma unroll
-                            for (int id = 0; id < ND; ++id)
-                                s += (double)out[ia * NB + ib][ic * ND + id] *
-                                     D[(size_t)(f2 + ib) * N + f4 + id];
-                        atomicAdd(&a.Kh[(size_t)(f1 + ia) * N + f3 + ic], fac * s);
-                    }
+                            for (int ia = A0; ia < A1; ++ia)
 #pragma unroll
-                for (int ib = 0; ib < NB; ++ib)
+                                for (int id = 0; id < ND; ++id)
+                                    sum += (double)out[(ia - A0) * NB + ib][(ic - C0) * ND + id] *
+                                           D[(size_t)(f1 + ia) * N + f4 + id];
+                            atomicAdd(&a.Kh[(size_t)(f2 + ib) * N + f3 + ic], fac * sum);
+                        }
+                    // K'_ad (partial over c)
 #pragma unroll
-                    for (int ic = 0; ic < NC; ++ic) {
-                        double s = 0.0;
+                    for (int ia = A0; ia < A1; ++ia)
 #pragma unroll
-                        for (int ia = 0; ia < NA; ++ia)
+                        for (int id = 0; id < ND; ++id) {
+                            double sum = 0.0;
 #pragma unroll
-                            for (int id = 0; id < ND; ++id)
-                                s += (double)out[ia * NB + ib][ic * ND + id] *
-                                     D[(size_t)(f1 + ia) * N + f4 + id];
-                        atomicAdd(&a.Kh[(size_t)(f2 + ib) * N + f3 + ic], fac * s);
-                    }
+                            for (int ib = 0; ib < NB; ++ib)
 #pragma unroll
-                for (int ia = 0; ia < NA; ++ia)
+                                for (int ic = C0; ic < C1; ++ic)
+                                    sum += (double)out[(ia - A0) * NB + ib][(ic - C0) * ND + id] *
+                                           D[(size_t)(f2 + ib) * N + f3 + ic];
+                            atomicAdd(&a.Kh[(size_t)(f1 + ia) * N + f4 + id], fac * sum);
+                        }
+                    // K'_bd (partial over a and c)
 #pragma unroll
-                    for (int id = 0; id < ND; ++id) {
-                        double s = 0.0;
+                    for (int ib = 0; ib < NB; ++ib)
 #pragma unroll
-                        for (int ib = 0; ib < NB; ++ib)
+                        for (int id = 0; id < ND; ++id) {
+                            double sum = 0.0;
 #pragma unroll
-                            for (int ic = 0; ic < NC; ++ic)
-                                s += (double)out[ia * NB + ib][ic * ND + id] *
-                                     D[(size_t)(f2 + ib) * N + f3 + ic];
-                        atomicAdd(&a.Kh[(size_t)(f1 + ia) * N + f4 + id], fac * s);
-                    }
+                            for (int ia = A0; ia < A1; ++ia)
 #pragma unroll
-                for (int ib = 0; ib < NB; ++ib)
-#pragma unroll
-                    for (int id = 0; id < ND; ++id) {
-                        double s = 0.0;
-#pragma unroll
-                        for (int ia = 0; ia < NA; ++ia)
-#pragma unroll
-                            for (int ic = 0; ic < NC; ++ic)
-                                s += (double)out[ia * NB + ib][ic * ND + id] *
-                                     D[(size_t)(f1 + ia) * N + f3 + ic];
-                        atomicAdd(&a.Kh[(size_t)(f2 + ib) * N + f4 + id], fac * s);
-                    }
+                                for (int ic = C0; ic < C1; ++ic)
+                                    sum += (double)out[(ia - A0) * NB + ib][(ic - C0) * ND + id] *
+                                           D[(size_t)(f1 + ia) * N + f3 + ic];
+                            atomicAdd(&a.Kh[(size_t)(f2 + ib) * N + f4 + id], fac * sum);
+                        }
+                }
             }
-        }
+        });
     }
 }
 
@@ -553,35 +618,35 @@ __global__ __launch_bounds__(64) void k_eri_wave(EriArgs a) {
     }
 }
 
-// Launch one class.  Kernel A for L <= 4, kernel B above.
-template <int LA, int LB, int LC, int LD>
-hipError_t launch_class(bool fp32, bool store, const EriArgs &a, hipStream_t s) {
+// Launch one class: kernel A (chunked) up to L = 6, kernel B above.
+constexpr int LANE_LIMIT_F64 = 27;   // live block values per lane, FP64
+constexpr int LANE_LIMIT_F32 = 54;   // same, FP32
+
+template <int LA, int LB, int LC, int LD, typename T, bool STORE>
+void launch_lane(dim3 g, dim3 b, const EriArgs &a, hipStream_t s) {
+    constexpr int lim = sizeof(T) == 8 ? LANE_LIMIT_F64 : LANE_LIMIT_F32;
+    constexpr int CA = chunk_a(LA, LB, LC, LD, lim), CC = chunk_c(LA, LB, LC, LD, lim);
+    hipLaunchKernelGGL((k_eri_lane<LA, LB, LC, LD, T, STORE, CA, CC>), g, b, 0, s, a);
+}
+
+template <int LA, int LB, int LC, int LD, typename T>
+hipError_t launch_class(bool store, const EriArgs &a, hipStream_t s) {
     const int ntile = store ? a.st_ntile : a.tl.ntile;
     if (ntile <= 0) return hipSuccess;
     constexpr int L = LA + LB + LC + LD;
-    if constexpr (L <= 4) {
+    if constexpr (L <= 6) {
         const int wpb = 4;
         int blocks = (ntile + wpb - 1) / wpb;
         if (blocks > 8192) blocks = 8192;
         dim3 g(blocks), b(64 * wpb);
-        if (fp32) {
-            if (store) hipLaunchKernelGGL((k_eri_lane<LA, LB, LC, LD, float, true>), g, b, 0, s, a);
-            else hipLaunchKernelGGL((k_eri_lane<LA, LB, LC, LD, float, false>), g, b, 0, s, a);
-        } else {
-            if (store) hipLaunchKernelGGL((k_eri_lane<LA, LB, LC, LD, double, true>), g, b, 0, s, a);
-            else hipLaunchKernelGGL((k_eri_lane<LA, LB, LC, LD, double, false>), g, b, 0, s, a);
-        }
+        if (store) launch_lane<LA, LB, LC, LD, T, true>(g, b, a, s);
+        else launch_lane<LA, LB, LC, LD, T, false>(g, b, a, s);
     } else {
         int blocks = ntile;
         if (blocks > 32768) blocks = 32768;
         dim3 g(blocks), b(64);
-        if (fp32) {
-            if (store) hipLaunchKernelGGL((k_eri_wave<LA, LB, LC, LD, float, true>), g, b, 0, s, a);
-            else hipLaunchKernelGGL((k_eri_wave<LA, LB, LC, LD, float, false>), g, b, 0, s, a);
-        } else {
-            if (store) hipLaunchKernelGGL((k_eri_wave<LA, LB, LC, LD, double, true>), g, b, 0, s, a);
-            else hipLaunchKernelGGL((k_eri_wave<LA, LB, LC, LD, double, false>), g, b, 0, s, a);
-        }
+        if (store) hipLaunchKernelGGL((k_eri_wave<LA, LB, LC, LD, T, true>), g, b, 0, s, a);
+        else hipLaunchKernelGGL((k_eri_wave<LA, LB, LC, LD, T, false>), g, b, 0, s, a);
     }
     return hipGetLastError();
 }

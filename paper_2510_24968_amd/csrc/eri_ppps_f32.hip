@@ -1,0 +1,10 @@
+// (pp|ps) class kernels, FP32 arithmetic.
+#include "eri_kernels.h"
+
+namespace fsim {
+
+hipError_t launch_eri_ppps_f32(bool store, const EriArgs &a, hipStream_t s) {
+    return launch_class<1, 1, 1, 0, float>(store, a, s);
+}
+
+}  // namespace fsim

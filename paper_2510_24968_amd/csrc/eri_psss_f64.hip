@@ -1,0 +1,10 @@
+// (ps|ss) class kernels, FP64 arithmetic.
+#include "eri_kernels.h"
+
+namespace fsim {
+
+hipError_t launch_eri_psss_f64(bool store, const EriArgs &a, hipStream_t s) {
+    return launch_class<1, 0, 0, 0, double>(store, a, s);
+}
+
+}  // namespace fsim

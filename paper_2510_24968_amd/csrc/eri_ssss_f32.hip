@@ -1,0 +1,10 @@
+// (ss|ss) class kernels, FP32 arithmetic.
+#include "eri_kernels.h"
+
+namespace fsim {
+
+hipError_t launch_eri_ssss_f32(bool store, const EriArgs &a, hipStream_t s) {
+    return launch_class<0, 0, 0, 0, float>(store, a, s);
+}
+
+}  // namespace fsim

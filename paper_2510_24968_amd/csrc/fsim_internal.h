@@ -177,12 +177,8 @@ hipError_t launch_build_pairs(const ShellsDev &sh, PairTable &t, const int *pair
 hipError_t launch_one_electron_impl(const ShellsDev &sh, const double *boys, int nbf,
                                     const int *bf_shell, const int *bf_comp, double *S,
                                     double *T, double *V, hipStream_t s);
-// per-bra-class launchers (eri_b<pc>.hip)
-hipError_t launch_eri_bra0(int ket_pc, bool fp32, bool store, const EriArgs &a, hipStream_t s);
-hipError_t launch_eri_bra1(int ket_pc, bool fp32, bool store, const EriArgs &a, hipStream_t s);
-hipError_t launch_eri_bra2(int ket_pc, bool fp32, bool store, const EriArgs &a, hipStream_t s);
-hipError_t launch_eri_bra3(int ket_pc, bool fp32, bool store, const EriArgs &a, hipStream_t s);
-hipError_t launch_eri_bra4(int ket_pc, bool fp32, bool store, const EriArgs &a, hipStream_t s);
-hipError_t launch_eri_bra5(int ket_pc, bool fp32, bool store, const EriArgs &a, hipStream_t s);
+// quartet-class dispatch (eri_dispatch.hip); bra_pc >= ket_pc
+hipError_t launch_eri(int bra_pc, int ket_pc, bool fp32, bool store, const EriArgs &a,
+                      hipStream_t s);
 
 }  // namespace fsim

@@ -46,13 +46,6 @@ __device__ __forceinline__ const double *etab<double>(const PairTable &t) { retu
 template <>
 __device__ __forceinline__ const float *etab<float>(const PairTable &t) { return t.Ef; }
 
-// Wave-uniform read of a table that no kernel writes while it runs, through
-// the constant address space so that it becomes a scalar (SMEM) load.
-template <typename T>
-__device__ __forceinline__ T ldu(const T *p) {
-    return *(const __attribute__((address_space(4))) T *)p;
-}
-
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
@@ -111,44 +104,55 @@ __device__ __forceinline__ int tile_bra(const TileList &tl, int tile) {
 // ===========================================================================
 // Kernel A: one lane per contracted quartet, everything unrolled at compile
 // time.  A wave owns a tile (one bra pair, up to 64 consecutive kets), so the
-// bra's exponents, centre and Hermite tensor are wave-uniform (scalar loads)
-// and the ket tables are read with unit stride across lanes.
+// bra's exponents, centre and Hermite tensor are wave-uniform and the ket
+// tables are read with unit stride across lanes.
 //
-// The block (ab|cd) is produced in chunks of CA bra components a and CC ket
-// components c, so that at most CA*NB x CC*ND values stay live in registers;
-// each chunk re-evaluates the Boys function and R^0 (cheap next to the
-// contraction) and is digested as soon as it is complete.
+// Loop order (the intermediate J_{tuv,k} of Sec. 2.5, summed over the ket
+// primitives before the bra contraction):
+//   for each bra primitive pair i:
+//       W_{tuv,cd} = sum over ket primitive pairs j of (-1)^{..} E^{cd}_j R^0_ij
+//       (ab|cd)   += sum_tuv E^{ab}_i W_{tuv,cd}
+// The block is produced in chunks of CA bra components a and CDC ket
+// component pairs cd, so that block, W and R^0 fit in registers; each chunk
+// re-evaluates the Boys function and R^0 and is digested when complete.
 // ===========================================================================
 __host__ __device__ constexpr int cmin(int a, int b) { return a < b ? a : b; }
 
-// chunk sizes: halve the ket, then the bra component range until the live
-// block is at most `limit` values
-__host__ __device__ constexpr int chunk_c(int la, int lb, int lc, int ld, int limit) {
-    int ca = ncart(la), cc = ncart(lc);
-    while (ca * ncart(lb) * cc * ncart(ld) > limit) {
-        if (cc > 1) cc = (cc + 1) / 2;
+// live values per lane of a chunk: block + W + R^0
+__host__ __device__ constexpr int lane_live(int la, int lb, int lc, int ld, int ca, int cdc) {
+    return ca * ncart(lb) * cdc + nherm(la + lb) * cdc + nherm(la + lb + lc + ld);
+}
+// chunk sizes: halve the cd range, then the a range, until the live set fits
+__host__ __device__ constexpr int chunk_cd(int la, int lb, int lc, int ld, int limit) {
+    int ca = ncart(la), cdc = ncart(lc) * ncart(ld);
+    while (lane_live(la, lb, lc, ld, ca, cdc) > limit) {
+        if (cdc > 1) cdc = (cdc + 1) / 2;
         else if (ca > 1) ca = (ca + 1) / 2;
         else break;
     }
-    return cc;
+    return cdc;
 }
 __host__ __device__ constexpr int chunk_a(int la, int lb, int lc, int ld, int limit) {
-    int ca = ncart(la), cc = ncart(lc);
-    while (ca * ncart(lb) * cc * ncart(ld) > limit) {
-        if (cc > 1) cc = (cc + 1) / 2;
+    int ca = ncart(la), cdc = ncart(lc) * ncart(ld);
+    while (lane_live(la, lb, lc, ld, ca, cdc) > limit) {
+        if (cdc > 1) cdc = (cdc + 1) / 2;
         else if (ca > 1) ca = (ca + 1) / 2;
         else break;
     }
     return ca;
 }
+__host__ __device__ constexpr int n_chunks(int la, int lb, int lc, int ld, int limit) {
+    const int ca = chunk_a(la, lb, lc, ld, limit), cdc = chunk_cd(la, lb, lc, ld, limit);
+    return ((ncart(la) + ca - 1) / ca) * ((ncart(lc) * ncart(ld) + cdc - 1) / cdc);
+}
 
-template <int LA, int LB, int LC, int LD, typename T, bool STORE, int CA, int CC>
+template <int LA, int LB, int LC, int LD, typename T, bool STORE, int CA, int CDC>
 __global__ __launch_bounds__(256) void k_eri_lane(EriArgs a) {
     constexpr int L = LA + LB + LC + LD, LAB = LA + LB;
     constexpr int NA = ncart(LA), NB = ncart(LB), NC = ncart(LC), ND = ncart(LD);
-    constexpr int NHAB = nherm(LAB), NH = nherm(L);
+    constexpr int NCD = NC * ND, NHAB = nherm(LAB), NH = nherm(L);
     constexpr int NEB = n_entries(LA, LB), NEK = n_entries(LC, LD);
-    constexpr int NCHA = (NA + CA - 1) / CA, NCHC = (NC + CC - 1) / CC;
+    constexpr int NCHA = (NA + CA - 1) / CA, NCHCD = (NCD + CDC - 1) / CDC;
     __shared__ double tab[BOYS_LDS];
     boys_stage(tab, a.boys, L);
     __syncthreads();
@@ -205,12 +209,11 @@ __global__ __launch_bounds__(256) void k_eri_lane(EriArgs a) {
             if (a.same_class && ket == bra) fac *= 0.5;
         }
 
-        static_for<NCHA * NCHC>([&](auto ch_) {
+        static_for<NCHA * NCHCD>([&](auto ch_) {
             constexpr int ch = decltype(ch_)::value;
-            constexpr int A0 = (ch / NCHC) * CA, A1 = cmin(A0 + CA, NA);
-            constexpr int C0 = (ch % NCHC) * CC, C1 = cmin(C0 + CC, NC);
-            constexpr int NAc = A1 - A0, NCc = C1 - C0;
-            constexpr int NABc = NAc * NB, NCDc = NCc * ND;
+            constexpr int A0 = (ch / NCHCD) * CA, A1 = cmin(A0 + CA, NA);
+            constexpr int CD0 = (ch % NCHCD) * CDC, CD1 = cmin(CD0 + CDC, NCD);
+            constexpr int NAc = A1 - A0, NABc = NAc * NB, NCDc = CD1 - CD0;
             T out[NABc][NCDc];
 #pragma unroll
             for (int x = 0; x < NABc; ++x)
@@ -218,24 +221,27 @@ __global__ __launch_bounds__(256) void k_eri_lane(EriArgs a) {
                 for (int y = 0; y < NCDc; ++y) out[x][y] = T(0);
 
             for (int i = 0; i < nbp; ++i) {
-                const double p = ldu(a.bra.p + i * nb + bra);
-                const double Px = ldu(a.bra.P + (i * 3 + 0) * nb + bra);
-                const double Py = ldu(a.bra.P + (i * 3 + 1) * nb + bra);
-                const double Pz = ldu(a.bra.P + (i * 3 + 2) * nb + bra);
-                const T *__restrict__ eb = Eb + (size_t)i * NEB * nb + bra;
+                const double p = a.bra.p[i * nb + bra];
+                const double Px = a.bra.P[(i * 3 + 0) * nb + bra];
+                const double Py = a.bra.P[(i * 3 + 1) * nb + bra];
+                const double Pz = a.bra.P[(i * 3 + 2) * nb + bra];
+                T W[NCDc][NHAB];
+#pragma unroll
+                for (int x = 0; x < NCDc; ++x)
+#pragma unroll
+                    for (int h = 0; h < NHAB; ++h) W[x][h] = T(0);
                 for (int j = 0; j < nkp; ++j) {
-                    // keep the bra tensor in scalar loads inside the loop
-                    // instead of letting it be hoisted into vector registers
-                    __asm__ __volatile__("" ::: "memory");
                     const double q = a.ket.p[j * nk + ket];
                     const double X = Px - a.ket.P[(j * 3 + 0) * nk + ket];
                     const double Y = Py - a.ket.P[(j * 3 + 1) * nk + ket];
                     const double Z = Pz - a.ket.P[(j * 3 + 2) * nk + ket];
-                    const double pq = p + q, alpha = p * q / pq;
+                    // 1/sqrt(p+q) once; 1/(p+q) and alpha = pq/(p+q) from it
+                    const double rs = rsqrt(p + q);
+                    const double alpha = p * q * (rs * rs);
                     double F[L + 1];
                     boys_eval<L>(alpha * (X * X + Y * Y + Z * Z), tab, F);
                     T src[L + 1];
-                    double m = 1.0 / sqrt(pq);
+                    double m = rs;
 #pragma unroll
                     for (int n = 0; n <= L; ++n) {
                         src[n] = T(F[n] * m);
@@ -246,13 +252,10 @@ __global__ __launch_bounds__(256) void k_eri_lane(EriArgs a) {
                     const T *__restrict__ ek = Ek + (size_t)j * NEK * nk + ket;
                     static_for<NCDc>([&](auto cdl_) {
                         constexpr int cdl = decltype(cdl_)::value;
-                        constexpr int cd = (C0 + cdl / ND) * ND + cdl % ND;
+                        constexpr int cd = CD0 + cdl;
                         constexpr int bx = box_dim(LC, LD, cd, 0), by = box_dim(LC, LD, cd, 1),
                                       bz = box_dim(LC, LD, cd, 2);
                         constexpr int eo = box_off(LC, LD, cd);
-                        T w[NHAB];
-#pragma unroll
-                        for (int h = 0; h < NHAB; ++h) w[h] = T(0);
                         static_for<bx + 1>([&](auto ta_) {
                             constexpr int ta = decltype(ta_)::value;
                             static_for<by + 1>([&](auto nu_) {
@@ -266,135 +269,157 @@ __global__ __launch_bounds__(256) void k_eri_lane(EriArgs a) {
                                         constexpr int h = decltype(h_)::value;
                                         constexpr int ri = hidx(hidx_t(h) + ta, hidx_u(h) + nu,
                                                                 hidx_v(h) + ph);
-                                        w[h] = fma(ev, r[ri], w[h]);
+                                        W[cdl][h] = fma(ev, r[ri], W[cdl][h]);
                                     });
                                 });
                             });
-                        });
-                        static_for<NABc>([&](auto abl_) {
-                            constexpr int abl = decltype(abl_)::value;
-                            constexpr int ab = (A0 + abl / NB) * NB + abl % NB;
-                            constexpr int ax = box_dim(LA, LB, ab, 0), ay = box_dim(LA, LB, ab, 1),
-                                          az = box_dim(LA, LB, ab, 2);
-                            constexpr int ao = box_off(LA, LB, ab);
-                            T acc = out[abl][cdl];
-                            static_for<ax + 1>([&](auto t_) {
-                                constexpr int t = decltype(t_)::value;
-                                static_for<ay + 1>([&](auto u_) {
-                                    constexpr int u = decltype(u_)::value;
-                                    static_for<az + 1>([&](auto v_) {
-                                        constexpr int v = decltype(v_)::value;
-                                        constexpr int e = ao + (t * (ay + 1) + u) * (az + 1) + v;
-                                        acc = fma(ldu(eb + (size_t)e * nb), w[hidx(t, u, v)], acc);
-                                    });
-                                });
-                            });
-                            out[abl][cdl] = acc;
                         });
                     });
                 }
+                // bra contraction, once per bra primitive pair
+                const T *__restrict__ eb = Eb + (size_t)i * NEB * nb + bra;
+                static_for<NABc>([&](auto abl_) {
+                    constexpr int abl = decltype(abl_)::value;
+                    constexpr int ab = (A0 + abl / NB) * NB + abl % NB;
+                    constexpr int ax = box_dim(LA, LB, ab, 0), ay = box_dim(LA, LB, ab, 1),
+                                  az = box_dim(LA, LB, ab, 2);
+                    constexpr int ao = box_off(LA, LB, ab);
+                    static_for<ax + 1>([&](auto t_) {
+                        constexpr int t = decltype(t_)::value;
+                        static_for<ay + 1>([&](auto u_) {
+                            constexpr int u = decltype(u_)::value;
+                            static_for<az + 1>([&](auto v_) {
+                                constexpr int v = decltype(v_)::value;
+                                constexpr int e = ao + (t * (ay + 1) + u) * (az + 1) + v;
+                                const T ebv = eb[(size_t)e * nb];
+                                static_for<NCDc>([&](auto cdl_) {
+                                    constexpr int cdl = decltype(cdl_)::value;
+                                    out[abl][cdl] = fma(ebv, W[cdl][hidx(t, u, v)], out[abl][cdl]);
+                                });
+                            });
+                        });
+                    });
+                });
             }
 
             if constexpr (STORE) {
                 if (active) {
-#pragma unroll
-                    for (int ia = A0; ia < A1; ++ia)
-#pragma unroll
-                        for (int ib = 0; ib < NB; ++ib)
-#pragma unroll
-                            for (int ic = C0; ic < C1; ++ic)
-#pragma unroll
-                                for (int id = 0; id < ND; ++id)
-                                    a.out[soff + ia * st0 + ib * st1 + ic * st2 + id * st3] =
-                                        (double)out[(ia - A0) * NB + ib][(ic - C0) * ND + id];
+                    static_for<NABc>([&](auto abl_) {
+                        constexpr int abl = decltype(abl_)::value;
+                        constexpr int ia = A0 + abl / NB, ib = abl % NB;
+                        static_for<NCDc>([&](auto cdl_) {
+                            constexpr int cdl = decltype(cdl_)::value;
+                            constexpr int ic = (CD0 + cdl) / ND, id = (CD0 + cdl) % ND;
+                            a.out[soff + ia * st0 + ib * st1 + ic * st2 + id * st3] =
+                                (double)out[abl][cdl];
+                        });
+                    });
                 }
             } else {
-                // J'_ab (partial over this chunk's c): pre-reduced over the wave
-#pragma unroll
-                for (int ia = A0; ia < A1; ++ia)
-#pragma unroll
-                    for (int ib = 0; ib < NB; ++ib) {
-                        double sum = 0.0;
-#pragma unroll
-                        for (int ic = C0; ic < C1; ++ic)
-#pragma unroll
-                            for (int id = 0; id < ND; ++id)
-                                sum += (double)out[(ia - A0) * NB + ib][(ic - C0) * ND + id] *
-                                       D[(size_t)(f3 + ic) * N + f4 + id];
-                        sum = wave_sum(2.0 * fac * sum);
-                        if (lane == 0) atomicAdd(&a.Jh[(size_t)(f1 + ia) * N + f2 + ib], sum);
-                    }
+                // J'_ab (partial over this chunk's cd): pre-reduced over the wave
+                static_for<NABc>([&](auto abl_) {
+                    constexpr int abl = decltype(abl_)::value;
+                    constexpr int ia = A0 + abl / NB, ib = abl % NB;
+                    double sum = 0.0;
+                    static_for<NCDc>([&](auto cdl_) {
+                        constexpr int cdl = decltype(cdl_)::value;
+                        constexpr int ic = (CD0 + cdl) / ND, id = (CD0 + cdl) % ND;
+                        sum += (double)out[abl][cdl] * D[(size_t)(f3 + ic) * N + f4 + id];
+                    });
+                    sum = wave_sum(2.0 * fac * sum);
+                    if (lane == 0) atomicAdd(&a.Jh[(size_t)(f1 + ia) * N + f2 + ib], sum);
+                });
                 if (active) {
                     // J'_cd (partial over this chunk's a)
-#pragma unroll
-                    for (int ic = C0; ic < C1; ++ic)
-#pragma unroll
-                        for (int id = 0; id < ND; ++id) {
-                            double sum = 0.0;
-#pragma unroll
-                            for (int ia = A0; ia < A1; ++ia)
-#pragma unroll
-                                for (int ib = 0; ib < NB; ++ib)
-                                    sum += (double)out[(ia - A0) * NB + ib][(ic - C0) * ND + id] *
-                                           D[(size_t)(f1 + ia) * N + f2 + ib];
-                            atomicAdd(&a.Jh[(size_t)(f3 + ic) * N + f4 + id], 2.0 * fac * sum);
+                    static_for<NCDc>([&](auto cdl_) {
+                        constexpr int cdl = decltype(cdl_)::value;
+                        constexpr int ic = (CD0 + cdl) / ND, id = (CD0 + cdl) % ND;
+                        double sum = 0.0;
+                        static_for<NABc>([&](auto abl_) {
+                            constexpr int abl = decltype(abl_)::value;
+                            constexpr int ia = A0 + abl / NB, ib = abl % NB;
+                            sum += (double)out[abl][cdl] * D[(size_t)(f1 + ia) * N + f2 + ib];
+                        });
+                        atomicAdd(&a.Jh[(size_t)(f3 + ic) * N + f4 + id], 2.0 * fac * sum);
+                    });
+                    // K'_xc for x in {a (with D_bd), b (with D_ad)} and every c in the chunk
+                    static_for<NC>([&](auto c_) {
+                        constexpr int ic = decltype(c_)::value;
+                        constexpr bool has_c = ic * ND + ND > CD0 && ic * ND < CD1;
+                        if constexpr (has_c) {
+                            static_for<NAc>([&](auto al_) {
+                                constexpr int al = decltype(al_)::value;
+                                double sum = 0.0;
+                                static_for<NB>([&](auto b_) {
+                                    constexpr int ib = decltype(b_)::value;
+                                    static_for<ND>([&](auto d_) {
+                                        constexpr int id = decltype(d_)::value;
+                                        constexpr int cd = ic * ND + id;
+                                        if constexpr (cd >= CD0 && cd < CD1)
+                                            sum += (double)out[al * NB + ib][cd - CD0] *
+                                                   D[(size_t)(f2 + ib) * N + f4 + id];
+                                    });
+                                });
+                                atomicAdd(&a.Kh[(size_t)(f1 + A0 + al) * N + f3 + ic], fac * sum);
+                            });
+                            static_for<NB>([&](auto b_) {
+                                constexpr int ib = decltype(b_)::value;
+                                double sum = 0.0;
+                                static_for<NAc>([&](auto al_) {
+                                    constexpr int al = decltype(al_)::value;
+                                    static_for<ND>([&](auto d_) {
+                                        constexpr int id = decltype(d_)::value;
+                                        constexpr int cd = ic * ND + id;
+                                        if constexpr (cd >= CD0 && cd < CD1)
+                                            sum += (double)out[al * NB + ib][cd - CD0] *
+                                                   D[(size_t)(f1 + A0 + al) * N + f4 + id];
+                                    });
+                                });
+                                atomicAdd(&a.Kh[(size_t)(f2 + ib) * N + f3 + ic], fac * sum);
+                            });
                         }
-                    // K'_ac (complete)
-#pragma unroll
-                    for (int ia = A0; ia < A1; ++ia)
-#pragma unroll
-                        for (int ic = C0; ic < C1; ++ic) {
-                            double sum = 0.0;
-#pragma unroll
-                            for (int ib = 0; ib < NB; ++ib)
-#pragma unroll
-                                for (int id = 0; id < ND; ++id)
-                                    sum += (double)out[(ia - A0) * NB + ib][(ic - C0) * ND + id] *
-                                           D[(size_t)(f2 + ib) * N + f4 + id];
-                            atomicAdd(&a.Kh[(size_t)(f1 + ia) * N + f3 + ic], fac * sum);
+                    });
+                    // K'_xd for x in {a (with D_bc), b (with D_ac)} and every d in the chunk
+                    static_for<ND>([&](auto d_) {
+                        constexpr int id = decltype(d_)::value;
+                        constexpr bool has_d = [] {
+                            for (int c = 0; c < NC; ++c)
+                                if (c * ND + id >= CD0 && c * ND + id < CD1) return true;
+                            return false;
+                        }();
+                        if constexpr (has_d) {
+                            static_for<NAc>([&](auto al_) {
+                                constexpr int al = decltype(al_)::value;
+                                double sum = 0.0;
+                                static_for<NB>([&](auto b_) {
+                                    constexpr int ib = decltype(b_)::value;
+                                    static_for<NC>([&](auto c_) {
+                                        constexpr int ic = decltype(c_)::value;
+                                        constexpr int cd = ic * ND + id;
+                                        if constexpr (cd >= CD0 && cd < CD1)
+                                            sum += (double)out[al * NB + ib][cd - CD0] *
+                                                   D[(size_t)(f2 + ib) * N + f3 + ic];
+                                    });
+                                });
+                                atomicAdd(&a.Kh[(size_t)(f1 + A0 + al) * N + f4 + id], fac * sum);
+                            });
+                            static_for<NB>([&](auto b_) {
+                                constexpr int ib = decltype(b_)::value;
+                                double sum = 0.0;
+                                static_for<NAc>([&](auto al_) {
+                                    constexpr int al = decltype(al_)::value;
+                                    static_for<NC>([&](auto c_) {
+                                        constexpr int ic = decltype(c_)::value;
+                                        constexpr int cd = ic * ND + id;
+                                        if constexpr (cd >= CD0 && cd < CD1)
+                                            sum += (double)out[al * NB + ib][cd - CD0] *
+                                                   D[(size_t)(f1 + A0 + al) * N + f3 + ic];
+                                    });
+                                });
+                                atomicAdd(&a.Kh[(size_t)(f2 + ib) * N + f4 + id], fac * sum);
+                            });
                         }
-                    // K'_bc (partial over a)
-#pragma unroll
-                    for (int ib = 0; ib < NB; ++ib)
-#pragma unroll
-                        for (int ic = C0; ic < C1; ++ic) {
-                            double sum = 0.0;
-#pragma unroll
-                            for (int ia = A0; ia < A1; ++ia)
-#pragma unroll
-                                for (int id = 0; id < ND; ++id)
-                                    sum += (double)out[(ia - A0) * NB + ib][(ic - C0) * ND + id] *
-                                           D[(size_t)(f1 + ia) * N + f4 + id];
-                            atomicAdd(&a.Kh[(size_t)(f2 + ib) * N + f3 + ic], fac * sum);
-                        }
-                    // K'_ad (partial over c)
-#pragma unroll
-                    for (int ia = A0; ia < A1; ++ia)
-#pragma unroll
-                        for (int id = 0; id < ND; ++id) {
-                            double sum = 0.0;
-#pragma unroll
-                            for (int ib = 0; ib < NB; ++ib)
-#pragma unroll
-                                for (int ic = C0; ic < C1; ++ic)
-                                    sum += (double)out[(ia - A0) * NB + ib][(ic - C0) * ND + id] *
-                                           D[(size_t)(f2 + ib) * N + f3 + ic];
-                            atomicAdd(&a.Kh[(size_t)(f1 + ia) * N + f4 + id], fac * sum);
-                        }
-                    // K'_bd (partial over a and c)
-#pragma unroll
-                    for (int ib = 0; ib < NB; ++ib)
-#pragma unroll
-                        for (int id = 0; id < ND; ++id) {
-                            double sum = 0.0;
-#pragma unroll
-                            for (int ia = A0; ia < A1; ++ia)
-#pragma unroll
-                                for (int ic = C0; ic < C1; ++ic)
-                                    sum += (double)out[(ia - A0) * NB + ib][(ic - C0) * ND + id] *
-                                           D[(size_t)(f1 + ia) * N + f3 + ic];
-                            atomicAdd(&a.Kh[(size_t)(f2 + ib) * N + f4 + id], fac * sum);
-                        }
+                    });
                 }
             }
         });
@@ -618,23 +643,35 @@ __global__ __launch_bounds__(64) void k_eri_wave(EriArgs a) {
     }
 }
 
-// Launch one class: kernel A (chunked) up to L = 6, kernel B above.
-constexpr int LANE_LIMIT_F64 = 27;   // live block values per lane, FP64
-constexpr int LANE_LIMIT_F32 = 54;   // same, FP32
+// Launch one class: kernel A when a chunking with at most MAX_CHUNKS chunks
+// keeps the live set per lane under the limit, kernel B otherwise.
+constexpr int LANE_LIMIT_F64 = 160;   // live values per lane, FP64
+constexpr int LANE_LIMIT_F32 = 160;   // same, FP32
+constexpr int MAX_CHUNKS = 24;
+
+template <typename T>
+__host__ __device__ constexpr int lane_limit() { return sizeof(T) == 8 ? LANE_LIMIT_F64 : LANE_LIMIT_F32; }
+
+template <int LA, int LB, int LC, int LD, typename T>
+__host__ __device__ constexpr bool use_lane_kernel() {
+    constexpr int lim = lane_limit<T>();
+    return lane_live(LA, LB, LC, LD, chunk_a(LA, LB, LC, LD, lim), chunk_cd(LA, LB, LC, LD, lim)) <=
+               lim &&
+           n_chunks(LA, LB, LC, LD, lim) <= MAX_CHUNKS;
+}
 
 template <int LA, int LB, int LC, int LD, typename T, bool STORE>
 void launch_lane(dim3 g, dim3 b, const EriArgs &a, hipStream_t s) {
-    constexpr int lim = sizeof(T) == 8 ? LANE_LIMIT_F64 : LANE_LIMIT_F32;
-    constexpr int CA = chunk_a(LA, LB, LC, LD, lim), CC = chunk_c(LA, LB, LC, LD, lim);
-    hipLaunchKernelGGL((k_eri_lane<LA, LB, LC, LD, T, STORE, CA, CC>), g, b, 0, s, a);
+    constexpr int lim = lane_limit<T>();
+    constexpr int CA = chunk_a(LA, LB, LC, LD, lim), CDC = chunk_cd(LA, LB, LC, LD, lim);
+    hipLaunchKernelGGL((k_eri_lane<LA, LB, LC, LD, T, STORE, CA, CDC>), g, b, 0, s, a);
 }
 
 template <int LA, int LB, int LC, int LD, typename T>
 hipError_t launch_class(bool store, const EriArgs &a, hipStream_t s) {
     const int ntile = store ? a.st_ntile : a.tl.ntile;
     if (ntile <= 0) return hipSuccess;
-    constexpr int L = LA + LB + LC + LD;
-    if constexpr (L <= 6) {
+    if constexpr (use_lane_kernel<LA, LB, LC, LD, T>()) {
         const int wpb = 4;
         int blocks = (ntile + wpb - 1) / wpb;
         if (blocks > 8192) blocks = 8192;

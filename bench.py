@@ -79,6 +79,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-mixed", action="store_true")
+    ap.add_argument("--tuning", default=None,
+                    help="autotuner cache (JSON); default: the committed one for this workload")
+    ap.add_argument("--autotune", action="store_true", help="tune in-process before timing")
     a = ap.parse_args()
     if a.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -101,6 +104,18 @@ def main():
     t0 = time.time()
     _, st = ctx.schwarz_screen()
     t_screen = time.time() - t0
+    from paper_2510_24968_amd import autotune
+    tuning_src = None
+    if a.autotune:
+        autotune.tune(ctx, ctx.core_guess())
+        tuning_src = "autotuned in-process"
+    else:
+        path = a.tuning or os.path.join(ROOT, "paper_2510_24968_amd", "tuning",
+                                        f"{a.workload}_mi355x.json")
+        if os.path.exists(path):
+            n = autotune.apply(ctx, autotune.load(path))
+            tuning_src = f"{os.path.relpath(path, ROOT)} ({n} class settings)"
+    log(f"tuning: {tuning_src or 'library defaults'}")
     log(f"nbf={ctx.nbf} setup {t_setup:.2f}s screen {t_screen:.2f}s kept {st['quartets_kept']}"
         f" of {st['quartets_total']} (fp32 part {st['quartets_fp32']})")
 
@@ -177,7 +192,8 @@ def main():
                    "tau_screen": w["tau"], "tau_fp32": tau32,
                    "quartets_screened": nq, "quartets_canonical": st["quartets_total"],
                    "prim_quartets_screened": st["prim_quartets_kept"],
-                   "parallelism": "single GPU"},
+                   "parallelism": "single GPU",
+                   "tuning": tuning_src or "library defaults"},
         "fock_build_s": fb,
         "scf_step_wall_s": wall64 / a.steps,
         "setup_s": t_setup,

@@ -190,6 +190,33 @@ fsim_status fsim_set_profiling(fsim_ctx *ctx, int32_t enable);
 fsim_status fsim_get_class_profile(fsim_ctx *ctx, fsim_class_profile *out, int32_t cap,
                                int32_t *count);
 
+/* Launch configuration of one quartet class and precision.  variant 0..2
+ * selects the one-lane-per-quartet kernel with a per-lane register budget of
+ * 96 / 128 / 160 live values (the block is then produced in chunks that fit;
+ * a budget that cannot be met falls back to variant 3), variant 3 the
+ * one-wave-per-quartet kernel.  waves_per_block is 1, 2 or 4. */
+typedef struct {
+    int32_t bra_class, ket_class;   /* pair classes, bra >= ket */
+    int32_t fp32;
+    int32_t variant;
+    int32_t waves_per_block;
+    int32_t kbra, kket;             /* max primitive pairs of the classes (cache key) */
+    int32_t pad;
+    double ms;                      /* measured time of the chosen setting (autotune) */
+} fsim_tuning;
+
+/* Replace the settings of the listed classes (host array of n records). */
+fsim_status fsim_set_tuning(fsim_ctx *ctx, const fsim_tuning *t, int32_t n);
+
+/* All 42 class/precision settings currently in use (host out, cap >= 42). */
+fsim_status fsim_get_tuning(fsim_ctx *ctx, fsim_tuning *out, int32_t cap, int32_t *n);
+
+/* Autotuner: time every variant x waves-per-block setting of every class
+ * with work, by per-launch HIP events over Fock builds at the density D
+ * (device, N x N) in precision prec on stream, and keep the fastest per
+ * class.  Needs a screen first.  Synchronises the stream. */
+fsim_status fsim_autotune(fsim_ctx *ctx, const double *D, fsim_precision prec, void *stream);
+
 /* Contracted ERI blocks (Eq. twoe-final summed over primitives) for n shell
  * quartets, evaluated by the Fock-build kernels but written out instead of
  * digested.  quartets: host [n*4] shell indices (a, b, c, d) in any order.

@@ -1,0 +1,90 @@
+"""Autotuner front end: runs the library's per-class variant search
+(fsim_autotune: every kernel variant x waves-per-block, timed per launch with
+HIP events on the workload itself) and keeps the result in a JSON cache keyed
+by quartet class, precision and primitive-pair counts, so that later contexts
+with the same shapes start from the tuned settings.
+
+    python -m paper_2510_24968_amd.autotune --workload water64 --out tuning.json
+"""
+
+import argparse
+import json
+import os
+import sys
+import time
+
+
+def cache_key(rec):
+    prec = "fp32" if rec["fp32"] else "fp64"
+    return f"{rec['cls']}|{prec}|K{rec['kbra']}x{rec['kket']}"
+
+
+def tune(ctx, D, precisions=("fp64", "mixed")):
+    """Run the search for each precision; returns {key: record}."""
+    table = {}
+    for prec in precisions:
+        print(f"[autotune] {prec}: searching variants x waves-per-block", file=sys.stderr,
+              flush=True)
+        t0 = time.time()
+        recs = ctx.autotune(D, prec)
+        print(f"[autotune] {prec}: done in {time.time() - t0:.1f}s", file=sys.stderr, flush=True)
+        for rec in recs:
+            if rec["ms"] > 0:
+                table[cache_key(rec)] = {k: rec[k] for k in
+                                         ("cls", "bra_class", "ket_class", "fp32", "variant",
+                                          "waves_per_block", "kbra", "kket", "ms")}
+    return table
+
+
+def save(table, path, meta=None):
+    data = {"meta": meta or {}, "entries": table}
+    tmp = path + ".tmp"
+    with open(tmp, "w") as f:
+        json.dump(data, f, indent=1, sort_keys=True)
+    os.replace(tmp, path)
+
+
+def load(path):
+    with open(path) as f:
+        return json.load(f)["entries"]
+
+
+def apply(ctx, table):
+    """Apply cached settings whose key matches this context's classes."""
+    cur = ctx.get_tuning()
+    recs = []
+    for r in cur:
+        hit = table.get(cache_key(r))
+        if hit is not None:
+            recs.append(dict(bra_class=r["bra_class"], ket_class=r["ket_class"], fp32=r["fp32"],
+                             variant=hit["variant"], waves_per_block=hit["waves_per_block"],
+                             ms=hit.get("ms", 0.0)))
+    if recs:
+        ctx.set_tuning(recs)
+    return len(recs)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--workload", default="water10")
+    ap.add_argument("--out", default=None)
+    a = ap.parse_args()
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    sys.path.insert(0, root)
+    import synth
+    from paper_2510_24968_amd import fsim
+    basis, w = synth.workload(a.workload)
+    ctx = fsim.Context(basis, tau=w["tau"], tau_fp32=w["tau_fp32"] or 1e-5)
+    ctx.schwarz_screen()
+    D = ctx.core_guess()
+    t0 = time.time()
+    table = tune(ctx, D)
+    print(f"tuned {len(table)} class settings in {time.time() - t0:.1f}s", file=sys.stderr)
+    out = a.out or os.path.join(os.getcwd(), f"tuning_{a.workload}.json")
+    save(table, out, {"workload": a.workload, "device": "MI355X (gfx950)"})
+    print(json.dumps({k: (v["variant"], v["waves_per_block"], round(v["ms"], 3))
+                      for k, v in sorted(table.items())}))
+
+
+if __name__ == "__main__":
+    main()

@@ -35,8 +35,19 @@ FLAGS = [
 ]
 
 
-def _compile(src, verbose):
+def _newest_header():
+    return max(os.path.getmtime(os.path.join(CSRC, f)) for f in os.listdir(CSRC)
+               if f.endswith(".h")) if os.path.isdir(CSRC) else 0.0
+
+
+def _compile(src, verbose, incremental=False):
     obj = os.path.join(BUILD, os.path.splitext(src)[0] + ".o")
+    if incremental and os.path.exists(obj):
+        t = os.path.getmtime(obj)
+        deps = max(os.path.getmtime(os.path.join(CSRC, src)), _newest_header(),
+                   os.path.getmtime(os.path.join(ROOT, "include", "fsim.h")))
+        if t > deps:
+            return obj
     cmd = [HIPCC] + FLAGS + ["-c", os.path.join(CSRC, src), "-o", obj]
     if src.endswith(".cpp"):
         cmd = [HIPCC] + FLAGS + ["-x", "hip", "-c", os.path.join(CSRC, src), "-o", obj]
@@ -49,11 +60,13 @@ def _compile(src, verbose):
     return obj
 
 
-def build(jobs=None, verbose=False):
+def build(jobs=None, verbose=False, incremental=False):
+    """Compile every source (or, with incremental=True, only those older than
+    their source or a header) and link libfsim.so."""
     os.makedirs(BUILD, exist_ok=True)
     jobs = jobs or min(len(SOURCES), max(1, (os.cpu_count() or 4)))
     with cf.ThreadPoolExecutor(jobs) as ex:
-        objs = list(ex.map(lambda s: _compile(s, verbose), SOURCES))
+        objs = list(ex.map(lambda s: _compile(s, verbose, incremental), SOURCES))
     tmp = LIB + ".tmp"
     cmd = [HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp] + objs + [
         "-L/opt/rocm/lib", "-lrocsolver", "-lrocblas", "-Wl,-rpath,/opt/rocm/lib"]
@@ -68,8 +81,9 @@ if __name__ == "__main__":
     ap = argparse.ArgumentParser()
     ap.add_argument("-j", type=int, default=None)
     ap.add_argument("--verbose", action="store_true")
+    ap.add_argument("--incremental", action="store_true")
     a = ap.parse_args()
     t0 = time.time()
-    build(a.j, a.verbose)
+    build(a.j, a.verbose, a.incremental)
     print(f"built {LIB} in {time.time() - t0:.1f}s")
     sys.exit(0)

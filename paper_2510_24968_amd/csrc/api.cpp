@@ -116,6 +116,11 @@ struct fsim_ctx {
     int *dinfo = nullptr;
     rocblas_handle blas = nullptr;
 
+    // launch settings per (bra class, ket class, fp32)
+    int variant[NPCLASS][NPCLASS][2];
+    int wpb[NPCLASS][NPCLASS][2];
+    double tuned_ms[NPCLASS][NPCLASS][2];
+
     // per-launch profiling
     bool profiling = false;
     std::vector<hipEvent_t> ev;
@@ -260,6 +265,13 @@ extern "C" fsim_status fsim_ctx_create(const fsim_basis *b, const fsim_options *
     };
     HIPCHK(hipGetDevice(&c->device));
     c->opt = *o;
+    for (int X = 0; X < NPCLASS; ++X)
+        for (int Y = 0; Y < NPCLASS; ++Y)
+            for (int f = 0; f < 2; ++f) {
+                c->variant[X][Y][f] = ERI_DEFAULT_VARIANT;
+                c->wpb[X][Y][f] = 4;
+                c->tuned_ms[X][Y][f] = 0.0;
+            }
     c->natom = b->natom;
     c->nshell = b->nshell;
     c->nelec = b->nelec;
@@ -517,7 +529,7 @@ static fsim_status run_store(fsim_ctx *c, std::vector<StoreTask> (&tasks)[NPCLAS
             a.out = out;
             a.boys = c->boys;
             a.nbf = c->nbf;
-            HIPCHK(launch_eri(X, Y, fp32, true, a, s));
+            HIPCHK(launch_eri(X, Y, fp32, true, ERI_DEFAULT_VARIANT, 4, a, s));
             HIPCHK(hipStreamSynchronize(s));
             hipFree(dbra);
             hipFree(dket);
@@ -849,7 +861,8 @@ static fsim_status fock_build(fsim_ctx *c, const double *D, double *F, double *J
                 a.Kh = c->Kh;
                 a.nbf = N;
                 a.boys = c->boys;
-                HIPCHK(launch_eri(X, Y, mixed && part == 1, false, a, s));
+                const int f32 = mixed && part == 1;
+                HIPCHK(launch_eri(X, Y, f32, false, c->variant[X][Y][f32], c->wpb[X][Y][f32], a, s));
                 if (c->profiling) HIPCHK(hipEventRecord(c->ev[nev++], s));
             }
         }
@@ -895,6 +908,109 @@ extern "C" fsim_status fsim_get_class_profile(fsim_ctx *c, fsim_class_profile *o
     if (out)
         for (int32_t k = 0; k < cap && k < *count; ++k) out[k] = c->prof[k];
     return FSIM_OK;
+}
+
+extern "C" fsim_status fsim_set_tuning(fsim_ctx *c, const fsim_tuning *t, int32_t n) {
+    if (!c || (n > 0 && !t)) return fail(FSIM_EINVAL, "NULL argument");
+    for (int32_t k = 0; k < n; ++k) {
+        const fsim_tuning &r = t[k];
+        if (r.bra_class < 0 || r.bra_class >= NPCLASS || r.ket_class < 0 ||
+            r.ket_class > r.bra_class || (r.fp32 != 0 && r.fp32 != 1))
+            return fail(FSIM_EINVAL, "tuning record names no quartet class");
+        if (r.variant < 0 || r.variant >= ERI_NVARIANT)
+            return fail(FSIM_EINVAL, "variant must be 0..3");
+        if (r.waves_per_block != 1 && r.waves_per_block != 2 && r.waves_per_block != 4)
+            return fail(FSIM_EINVAL, "waves_per_block must be 1, 2 or 4");
+    }
+    for (int32_t k = 0; k < n; ++k) {
+        const fsim_tuning &r = t[k];
+        c->variant[r.bra_class][r.ket_class][r.fp32] = r.variant;
+        c->wpb[r.bra_class][r.ket_class][r.fp32] = r.waves_per_block;
+        c->tuned_ms[r.bra_class][r.ket_class][r.fp32] = r.ms;
+    }
+    return FSIM_OK;
+}
+
+extern "C" fsim_status fsim_get_tuning(fsim_ctx *c, fsim_tuning *out, int32_t cap, int32_t *n) {
+    if (!c || !n) return fail(FSIM_EINVAL, "NULL argument");
+    int32_t k = 0;
+    for (int X = 0; X < NPCLASS; ++X)
+        for (int Y = 0; Y <= X; ++Y)
+            for (int f = 0; f < 2; ++f) {
+                if (out && k < cap) {
+                    fsim_tuning r{};
+                    r.bra_class = X;
+                    r.ket_class = Y;
+                    r.fp32 = f;
+                    r.variant = c->variant[X][Y][f];
+                    r.waves_per_block = c->wpb[X][Y][f];
+                    r.kbra = c->screened ? c->kept[X].kmax : c->all[X].kmax;
+                    r.kket = c->screened ? c->kept[Y].kmax : c->all[Y].kmax;
+                    r.ms = c->tuned_ms[X][Y][f];
+                    out[k] = r;
+                }
+                ++k;
+            }
+    *n = k;
+    return FSIM_OK;
+}
+
+extern "C" fsim_status fsim_autotune(fsim_ctx *c, const double *D, fsim_precision prec,
+                                     void *stream) {
+    if (!c || !D) return fail(FSIM_EINVAL, "NULL argument");
+    if (!c->screened) return fail(FSIM_ESTATE, "fsim_schwarz_screen must run before autotuning");
+    hipStream_t s = (hipStream_t)stream;
+    const bool was = c->profiling;
+    c->profiling = true;
+    double best[NPCLASS][NPCLASS][2];
+    int bv[NPCLASS][NPCLASS][2], bw[NPCLASS][NPCLASS][2];
+    for (int X = 0; X < NPCLASS; ++X)
+        for (int Y = 0; Y < NPCLASS; ++Y)
+            for (int f = 0; f < 2; ++f) {
+                best[X][Y][f] = 1e300;
+                bv[X][Y][f] = c->variant[X][Y][f];
+                bw[X][Y][f] = c->wpb[X][Y][f];
+            }
+    const int wpbs[3] = {1, 2, 4};
+    fsim_status st = FSIM_OK;
+    // one warm-up build
+    st = fock_build(c, D, c->F, nullptr, nullptr, nullptr, prec, s);
+    for (int v = 0; v < ERI_NVARIANT && st == FSIM_OK; ++v)
+        for (int w = 0; w < 3 && st == FSIM_OK; ++w) {
+            if (v == ERI_NVARIANT - 1 && w > 0) break;   // the wave kernel ignores it
+            // the wave kernel is only a candidate for the high angular-momentum
+            // classes (L >= 5); elsewhere it is far slower, so those classes keep
+            // a lane variant during that pass and are not scored in it
+            const bool wave = v == ERI_NVARIANT - 1;
+            auto Ltot = [](int X, int Y) {
+                return pclass_l1(X) + pclass_l2(X) + pclass_l1(Y) + pclass_l2(Y);
+            };
+            for (int X = 0; X < NPCLASS; ++X)
+                for (int Y = 0; Y < NPCLASS; ++Y)
+                    for (int f = 0; f < 2; ++f) {
+                        const bool cand = !wave || Ltot(X, Y) >= 5;
+                        c->variant[X][Y][f] = cand ? v : ERI_DEFAULT_VARIANT;
+                        c->wpb[X][Y][f] = wpbs[w];
+                    }
+            st = fock_build(c, D, c->F, nullptr, nullptr, nullptr, prec, s);
+            if (st != FSIM_OK) break;
+            for (const auto &r : c->prof)
+                if ((!wave || Ltot(r.bra_class, r.ket_class) >= 5) &&
+                    r.ms < best[r.bra_class][r.ket_class][r.fp32]) {
+                    best[r.bra_class][r.ket_class][r.fp32] = r.ms;
+                    bv[r.bra_class][r.ket_class][r.fp32] = v;
+                    bw[r.bra_class][r.ket_class][r.fp32] = wpbs[w];
+                }
+        }
+    for (int X = 0; X < NPCLASS; ++X)
+        for (int Y = 0; Y < NPCLASS; ++Y)
+            for (int f = 0; f < 2; ++f) {
+                c->variant[X][Y][f] = bv[X][Y][f];
+                c->wpb[X][Y][f] = bw[X][Y][f];
+                if (best[X][Y][f] < 1e299) c->tuned_ms[X][Y][f] = best[X][Y][f];
+            }
+    c->profiling = was;
+    return st;
 }
 
 extern "C" fsim_status fsim_core_guess(fsim_ctx *c, double *D, void *stream) {

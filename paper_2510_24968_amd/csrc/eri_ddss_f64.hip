@@ -3,8 +3,9 @@
 
 namespace fsim {
 
-hipError_t launch_eri_ddss_f64(bool store, const EriArgs &a, hipStream_t s) {
-    return launch_class<2, 2, 0, 0, double>(store, a, s);
+hipError_t launch_eri_ddss_f64(bool store, int variant, int wpb, const EriArgs &a,
+                                 hipStream_t s) {
+    return launch_class<2, 2, 0, 0, double>(store, variant, wpb, a, s);
 }
 
 }  // namespace fsim

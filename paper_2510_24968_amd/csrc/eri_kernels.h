@@ -643,47 +643,62 @@ __global__ __launch_bounds__(64) void k_eri_wave(EriArgs a) {
     }
 }
 
-// Launch one class: kernel A when a chunking with at most MAX_CHUNKS chunks
-// keeps the live set per lane under the limit, kernel B otherwise.
-constexpr int LANE_LIMIT_F64 = 160;   // live values per lane, FP64
-constexpr int LANE_LIMIT_F32 = 160;   // same, FP32
+// Launch variants.  A variant fixes the per-lane register budget of kernel A
+// (live block + W + R^0 values; the chunking follows from it); the last one
+// is kernel B.  A budget whose chunking does not fit, or needs more than
+// MAX_CHUNKS chunks, also falls back to kernel B.  The autotuner picks a
+// variant and the waves per block for every class and precision.
+constexpr int NVARIANT = 4;
+constexpr int VARIANT_WAVE = NVARIANT - 1;
+constexpr int DEFAULT_VARIANT = 1;
+__host__ __device__ constexpr int variant_budget(int v) {
+    return v == 0 ? 96 : (v == 1 ? 128 : (v == 2 ? 160 : 0));
+}
 constexpr int MAX_CHUNKS = 24;
 
-template <typename T>
-__host__ __device__ constexpr int lane_limit() { return sizeof(T) == 8 ? LANE_LIMIT_F64 : LANE_LIMIT_F32; }
-
-template <int LA, int LB, int LC, int LD, typename T>
-__host__ __device__ constexpr bool use_lane_kernel() {
-    constexpr int lim = lane_limit<T>();
-    return lane_live(LA, LB, LC, LD, chunk_a(LA, LB, LC, LD, lim), chunk_cd(LA, LB, LC, LD, lim)) <=
-               lim &&
-           n_chunks(LA, LB, LC, LD, lim) <= MAX_CHUNKS;
+template <int LA, int LB, int LC, int LD, int BUDGET>
+__host__ __device__ constexpr bool lane_fits() {
+    return BUDGET > 0 &&
+           lane_live(LA, LB, LC, LD, chunk_a(LA, LB, LC, LD, BUDGET),
+                     chunk_cd(LA, LB, LC, LD, BUDGET)) <= BUDGET &&
+           n_chunks(LA, LB, LC, LD, BUDGET) <= MAX_CHUNKS;
 }
 
 template <int LA, int LB, int LC, int LD, typename T, bool STORE>
-void launch_lane(dim3 g, dim3 b, const EriArgs &a, hipStream_t s) {
-    constexpr int lim = lane_limit<T>();
-    constexpr int CA = chunk_a(LA, LB, LC, LD, lim), CDC = chunk_cd(LA, LB, LC, LD, lim);
-    hipLaunchKernelGGL((k_eri_lane<LA, LB, LC, LD, T, STORE, CA, CDC>), g, b, 0, s, a);
+void launch_wave_kernel(int ntile, const EriArgs &a, hipStream_t s) {
+    int blocks = ntile;
+    if (blocks > 32768) blocks = 32768;
+    hipLaunchKernelGGL((k_eri_wave<LA, LB, LC, LD, T, STORE>), dim3(blocks), dim3(64), 0, s, a);
+}
+
+template <int LA, int LB, int LC, int LD, typename T, bool STORE, int BUDGET>
+void launch_budget(int ntile, int wpb, const EriArgs &a, hipStream_t s) {
+    if constexpr (lane_fits<LA, LB, LC, LD, BUDGET>()) {
+        constexpr int CA = chunk_a(LA, LB, LC, LD, BUDGET), CDC = chunk_cd(LA, LB, LC, LD, BUDGET);
+        int blocks = (ntile + wpb - 1) / wpb;
+        if (blocks > 8192) blocks = 8192;
+        hipLaunchKernelGGL((k_eri_lane<LA, LB, LC, LD, T, STORE, CA, CDC>), dim3(blocks),
+                           dim3(64 * wpb), 0, s, a);
+    } else {
+        launch_wave_kernel<LA, LB, LC, LD, T, STORE>(ntile, a, s);
+    }
 }
 
 template <int LA, int LB, int LC, int LD, typename T>
-hipError_t launch_class(bool store, const EriArgs &a, hipStream_t s) {
+hipError_t launch_class(bool store, int variant, int wpb, const EriArgs &a, hipStream_t s) {
     const int ntile = store ? a.st_ntile : a.tl.ntile;
     if (ntile <= 0) return hipSuccess;
-    if constexpr (use_lane_kernel<LA, LB, LC, LD, T>()) {
-        const int wpb = 4;
-        int blocks = (ntile + wpb - 1) / wpb;
-        if (blocks > 8192) blocks = 8192;
-        dim3 g(blocks), b(64 * wpb);
-        if (store) launch_lane<LA, LB, LC, LD, T, true>(g, b, a, s);
-        else launch_lane<LA, LB, LC, LD, T, false>(g, b, a, s);
-    } else {
-        int blocks = ntile;
-        if (blocks > 32768) blocks = 32768;
-        dim3 g(blocks), b(64);
-        if (store) hipLaunchKernelGGL((k_eri_wave<LA, LB, LC, LD, T, true>), g, b, 0, s, a);
-        else hipLaunchKernelGGL((k_eri_wave<LA, LB, LC, LD, T, false>), g, b, 0, s, a);
+    if (wpb < 1 || wpb > 4) wpb = 4;
+    if (store) {
+        // stored blocks (screening, per-integral checks) use the default variant
+        launch_budget<LA, LB, LC, LD, T, true, variant_budget(DEFAULT_VARIANT)>(ntile, wpb, a, s);
+        return hipGetLastError();
+    }
+    switch (variant) {
+        case 0: launch_budget<LA, LB, LC, LD, T, false, variant_budget(0)>(ntile, wpb, a, s); break;
+        case 1: launch_budget<LA, LB, LC, LD, T, false, variant_budget(1)>(ntile, wpb, a, s); break;
+        case 2: launch_budget<LA, LB, LC, LD, T, false, variant_budget(2)>(ntile, wpb, a, s); break;
+        default: launch_wave_kernel<LA, LB, LC, LD, T, false>(ntile, a, s); break;
     }
     return hipGetLastError();
 }

@@ -63,7 +63,15 @@ class _ClassProfile(ctypes.Structure):
                 ("flops", ctypes.c_double), ("ms", ctypes.c_double)]
 
 
+class _Tuning(ctypes.Structure):
+    _fields_ = [("bra_class", ctypes.c_int32), ("ket_class", ctypes.c_int32),
+                ("fp32", ctypes.c_int32), ("variant", ctypes.c_int32),
+                ("waves_per_block", ctypes.c_int32), ("kbra", ctypes.c_int32),
+                ("kket", ctypes.c_int32), ("pad", ctypes.c_int32), ("ms", ctypes.c_double)]
+
+
 PAIR_CLASS = ("ss", "ps", "pp", "ds", "dp", "dd")
+NVARIANT = 4
 
 
 def _struct_dict(s):
@@ -95,6 +103,9 @@ def lib():
         "fsim_scf_reset": [vp],
         "fsim_eri_quartets": [vp, i64, vp, vp, vp, ctypes.c_int, vp],
         "fsim_set_profiling": [vp, i32],
+        "fsim_set_tuning": [vp, vp, i32],
+        "fsim_get_tuning": [vp, vp, i32, ctypes.POINTER(i32)],
+        "fsim_autotune": [vp, vp, ctypes.c_int, vp],
         "fsim_get_class_profile": [vp, vp, i32, ctypes.POINTER(i32)],
     }
     for name, args in sigs.items():
@@ -232,6 +243,38 @@ class Context:
             d["cls"] = f"({PAIR_CLASS[d['bra_class']]}|{PAIR_CLASS[d['ket_class']]})"
             out.append(d)
         return out
+
+    def get_tuning(self):
+        """Launch settings of every (bra class, ket class, precision)."""
+        n = ctypes.c_int32()
+        arr = (_Tuning * 64)()
+        _check(lib().fsim_get_tuning(self.h, arr, 64, ctypes.byref(n)))
+        out = []
+        for k in range(n.value):
+            d = _struct_dict(arr[k])
+            d["cls"] = f"({PAIR_CLASS[d['bra_class']]}|{PAIR_CLASS[d['ket_class']]})"
+            out.append(d)
+        return out
+
+    def set_tuning(self, records):
+        """Apply a list of tuning dicts (bra_class, ket_class, fp32, variant,
+        waves_per_block[, ms])."""
+        arr = (_Tuning * max(1, len(records)))()
+        for k, r in enumerate(records):
+            arr[k] = _Tuning(int(r["bra_class"]), int(r["ket_class"]), int(r["fp32"]),
+                             int(r["variant"]), int(r["waves_per_block"]), 0, 0, 0,
+                             float(r.get("ms", 0.0)))
+        _check(lib().fsim_set_tuning(self.h, arr, len(records)))
+
+    def set_all_variants(self, variant, waves_per_block=4):
+        recs = [dict(bra_class=x, ket_class=y, fp32=f, variant=variant,
+                     waves_per_block=waves_per_block)
+                for x in range(6) for y in range(x + 1) for f in (0, 1)]
+        self.set_tuning(recs)
+
+    def autotune(self, D, precision="fp64"):
+        _check(lib().fsim_autotune(self.h, _ptr(D), _PREC[precision], _stream()))
+        return self.get_tuning()
 
     def eri_quartets(self, quartets, precision="fp64"):
         """Contracted Cartesian blocks (numpy) for an (n, 4) array of shell indices."""

@@ -312,3 +312,42 @@ def test_many_contexts_in_a_row():
             worst = max(worst, float(np.max(np.abs(g - B.eri_block(*q)))))
         print(f"context {seed}: worst so far {worst:.2e}", flush=True)
     assert worst < 1e-12
+
+
+@pytest.mark.parametrize("variant", [0, 1, 2, 3])
+def test_every_kernel_variant_matches_oracle(variant):
+    """Each launch variant the autotuner may pick (three register budgets of
+    the lane kernel, the wave kernel) and each waves-per-block setting gives
+    the oracle's J and K for every quartet class."""
+    b = spd_molecule()
+    ctx = _ctx(b)
+    ctx.schwarz_screen(tau=0.0)
+    D = _random_density(ctx.nbf, 5)
+    Jo, Ko = oracle.Basis(b).fock_jk(D, tau=0.0)
+    for wpb in (1, 2, 4):
+        ctx.set_all_variants(variant, wpb)
+        for prec, tol in (("fp64", 1e-11), ("mixed", 1e-11)):
+            r = ctx.fock_build(_dev(D), precision=prec, want_jk=True)
+            assert np.max(np.abs(r["J"].cpu().numpy() - Jo)) < tol, (variant, wpb, prec)
+            assert np.max(np.abs(r["K"].cpu().numpy() - Ko)) < tol, (variant, wpb, prec)
+
+
+def test_autotune_then_parity():
+    from paper_2510_24968_amd import autotune
+    b = synth.water_cluster(3, 4)
+    tau = 1e-10
+    ctx = _ctx(b, tau=tau, tau_fp32=1e-5)
+    ctx.schwarz_screen()
+    D0 = ctx.core_guess()
+    table = autotune.tune(ctx, D0)
+    assert len(table) > 0
+    assert all(0 <= r["variant"] < 4 and r["waves_per_block"] in (1, 2, 4) for r in table.values())
+    D = D0.cpu().numpy()
+    Jo, Ko = oracle.Basis(b).fock_jk(D, tau=tau)
+    r = ctx.fock_build(D0, want_jk=True)
+    assert np.max(np.abs(r["J"].cpu().numpy() - Jo)) < 1e-11
+    assert np.max(np.abs(r["K"].cpu().numpy() - Ko)) < 1e-11
+    # the cache round-trips onto a fresh context
+    ctx2 = _ctx(b, tau=tau, tau_fp32=1e-5)
+    ctx2.schwarz_screen()
+    assert autotune.apply(ctx2, table) > 0

@@ -227,6 +227,42 @@ fsim_status fsim_eri_quartets(fsim_ctx *ctx, int64_t n, const int32_t *quartets,
                               const int64_t *offsets, double *out, fsim_precision prec,
                               void *stream);
 
+/* ---- batches of molecules --------------------------------------------- */
+
+/* Context over nmol independent molecules (host array of bases).  Shell
+ * pairs and quartets never mix molecules; one class launch serves every
+ * molecule's quartets (the kets of each pair class are ordered by molecule,
+ * then Q, so every bra's ket range stays inside its molecule).  Every N x N
+ * argument of the other entry points becomes a packed array: molecule m's
+ * N_m x N_m row-major block at element offset offsets[m] (fsim_batch_layout).
+ * fsim_scf_step runs the SCF step on all molecules at once (zero-padded
+ * blocks, strided-batched rocBLAS / rocSOLVER dsyevd, DIIS per molecule);
+ * its info aggregates (sum of energies, max RMS(dD), all converged) and
+ * fsim_batch_scf_info gives the per-molecule records.  fsim_eri_quartets
+ * accepts only quartets within one molecule. */
+fsim_status fsim_batch_create(const fsim_basis *mols, int32_t nmol, const fsim_options *opt,
+                              fsim_ctx **out);
+
+/* Layout of a context (one molecule: nmol = 1, offset 0).  Any pointer may
+ * be NULL; nbf/offsets/enuc are host arrays of nmol entries. */
+fsim_status fsim_batch_layout(const fsim_ctx *ctx, int32_t *nmol, int32_t *nbf, int64_t *offsets,
+                              double *enuc, int64_t *packed);
+
+/* Per-molecule electronic energies of the last Fock build that computed an
+ * energy (host array of nmol). */
+fsim_status fsim_batch_energies(const fsim_ctx *ctx, double *E_elec);
+
+/* Per-molecule records of the last batched fsim_scf_step (host array of nmol). */
+fsim_status fsim_batch_scf_info(const fsim_ctx *ctx, fsim_scf_info *info);
+
+/* Capture the Fock build (zeroing kernels, every class kernel, the Fock
+ * assembly) once per precision as a hipGraph on an internal stream and
+ * replay it for every later fsim_fock_build / fsim_scf_step that asks for F
+ * without J and K.  The caller's stream is ordered before and after the
+ * replay with events.  Rescreening drops the graphs.  enable = 0 returns to
+ * direct launches. */
+fsim_status fsim_set_graph(fsim_ctx *ctx, int32_t enable);
+
 #ifdef __cplusplus
 }
 #endif

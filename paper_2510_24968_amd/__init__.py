@@ -7,6 +7,7 @@ include/fsim.h); this package is its thin Python binding."""
 from .fsim import (  # noqa: F401
     FSIM_FP64,
     FSIM_MIXED,
+    Batch,
     Context,
     FsimError,
     LIBPATH,

@@ -89,8 +89,33 @@ struct fsim_ctx {
     fsim_options opt{};
     int natom = 0, nshell = 0, nbf = 0, nelec = 0, nocc = 0;
     std::vector<double> xyz, Z, exps, coefs;
-    std::vector<int> sh_atom, sh_l, sh_nprim, sh_prim0, sh_bf0;
+    std::vector<int> sh_atom, sh_l, sh_nprim, sh_prim0, sh_bf0, sh_mol;
     double enuc = 0.0;
+
+    // molecules (one for fsim_ctx_create, many for fsim_batch_create): each
+    // keeps its N_m x N_m matrices at a packed offset
+    int nmol = 1, nmax = 0;
+    long long packed = 0;
+    std::vector<int> mol_n, mol_nocc, mol_bf0, mol_atom0, mol_natom, mol_shell0, mol_nshell;
+    std::vector<long long> mol_off;
+    std::vector<double> mol_enuc;
+    int *d_mol_n = nullptr, *d_nocc = nullptr;
+    long long *d_mol_off = nullptr;
+    double *Emol = nullptr;           // [nmol] electronic energies of the last build
+    std::vector<double> Emol_host;
+    // batched SCF (nmol > 1): zero-padded N_max x N_max blocks
+    double *pS = nullptr, *pX = nullptr, *pH = nullptr, *pF = nullptr, *pD = nullptr,
+           *pT1 = nullptr, *pT2 = nullptr, *pEig = nullptr, *pErr = nullptr, *pRed = nullptr;
+    std::vector<double *> pdF, pdE;
+    std::vector<double> Bb;            // [nmol][m][m]
+    std::vector<double> Eprev_mol;
+    std::vector<fsim_scf_info> mol_info;
+    // captured Fock build (hipGraph), one per precision
+    bool graph_enabled = false;
+    hipStream_t gstream = nullptr;
+    hipGraphExec_t gexec[2] = {nullptr, nullptr};
+    hipEvent_t gev[2] = {nullptr, nullptr};
+    double *gD = nullptr, *gF = nullptr;
 
     DevPool pool;        // lives as long as the context
     DevPool screen_pool; // replaced by every screen
@@ -137,6 +162,15 @@ struct fsim_ctx {
 
 static int ncart_h(int l) { return (l + 1) * (l + 2) / 2; }
 
+static MolLayout layout_of(const fsim_ctx *c) {
+    MolLayout L;
+    L.nmol = c->nmol;
+    L.nmax = c->nmax;
+    L.off = c->d_mol_off;
+    L.n = c->d_mol_n;
+    return L;
+}
+
 // ---------------------------------------------------------------------------
 // helpers
 // ---------------------------------------------------------------------------
@@ -154,6 +188,7 @@ static fsim_status alloc_table(DevPool &pool, PairTable &t, int l1, int l2, int 
     HIPCHK(pool.alloc(&t.bf1, n));
     HIPCHK(pool.alloc(&t.bf2, n));
     HIPCHK(pool.alloc(&t.nprim, n));
+    HIPCHK(pool.alloc(&t.mol, n));
     HIPCHK(pool.alloc(&t.Q, n));
     HIPCHK(pool.alloc(&t.p, (size_t)kmax * n));
     HIPCHK(pool.alloc(&t.P, (size_t)kmax * 3 * n));
@@ -254,72 +289,27 @@ static fsim_status validate(const fsim_basis *b, const fsim_options *o) {
     return FSIM_OK;
 }
 
-extern "C" fsim_status fsim_ctx_create(const fsim_basis *b, const fsim_options *o, fsim_ctx **out) {
+static fsim_status batched_orthogonaliser(fsim_ctx *c, hipStream_t s);
+
+// Context over nmol molecules.  Shells, pairs and quartets never mix
+// molecules; every matrix is kept per molecule at a packed offset.
+static fsim_status create_impl(const fsim_basis *mols, int nmol, const fsim_options *o,
+                               fsim_ctx **out) {
     if (!out) return fail(FSIM_EINVAL, "out must not be NULL");
     *out = nullptr;
-    STCHK(validate(b, o));
+    if (!mols || nmol < 1) return fail(FSIM_EINVAL, "need at least one molecule");
+    for (int m = 0; m < nmol; ++m) {
+        fsim_status v = validate(&mols[m], o);
+        if (v != FSIM_OK) {
+            if (nmol > 1) g_err = "molecule " + std::to_string(m) + ": " + g_err;
+            return v;
+        }
+    }
     fsim_ctx *c = new fsim_ctx();
     auto cleanup = [&](fsim_status st) {
         fsim_ctx_destroy(c);
         return st;
     };
-    HIPCHK(hipGetDevice(&c->device));
-    c->opt = *o;
-    for (int X = 0; X < NPCLASS; ++X)
-        for (int Y = 0; Y < NPCLASS; ++Y)
-            for (int f = 0; f < 2; ++f) {
-                c->variant[X][Y][f] = ERI_DEFAULT_VARIANT;
-                c->wpb[X][Y][f] = 4;
-                c->tuned_ms[X][Y][f] = 0.0;
-            }
-    c->natom = b->natom;
-    c->nshell = b->nshell;
-    c->nelec = b->nelec;
-    c->nocc = b->nelec / 2;
-    c->xyz.assign(b->xyz, b->xyz + 3 * b->natom);
-    c->Z.assign(b->Z, b->Z + b->natom);
-    c->sh_atom.assign(b->shell_atom, b->shell_atom + b->nshell);
-    c->sh_l.assign(b->shell_l, b->shell_l + b->nshell);
-    c->sh_nprim.assign(b->shell_nprim, b->shell_nprim + b->nshell);
-    c->sh_prim0.assign(b->shell_prim0, b->shell_prim0 + b->nshell);
-    int nprim_tot = 0;
-    for (int s = 0; s < c->nshell; ++s)
-        nprim_tot = std::max(nprim_tot, c->sh_prim0[s] + c->sh_nprim[s]);
-    c->exps.assign(b->exps, b->exps + nprim_tot);
-    c->coefs.assign(b->coefs, b->coefs + nprim_tot);
-    c->sh_bf0.resize(c->nshell);
-    int nbf = 0;
-    std::vector<int> bf_shell, bf_comp;
-    for (int s = 0; s < c->nshell; ++s) {
-        c->sh_bf0[s] = nbf;
-        for (int k = 0; k < ncart_h(c->sh_l[s]); ++k) {
-            bf_shell.push_back(s);
-            bf_comp.push_back(k);
-        }
-        nbf += ncart_h(c->sh_l[s]);
-    }
-    c->nbf = nbf;
-    const int N = nbf;
-    const size_t N2 = (size_t)N * N;
-
-    // nuclear repulsion
-    double en = 0.0;
-    for (int A = 0; A < c->natom; ++A)
-        for (int B = 0; B < A; ++B) {
-            const double dx = c->xyz[3 * A] - c->xyz[3 * B], dy = c->xyz[3 * A + 1] - c->xyz[3 * B + 1],
-                         dz = c->xyz[3 * A + 2] - c->xyz[3 * B + 2];
-            en += c->Z[A] * c->Z[B] / std::sqrt(dx * dx + dy * dy + dz * dz);
-        }
-    c->enuc = en;
-
-    // shells on the device
-    std::vector<double> shxyz(3 * c->nshell);
-    for (int s = 0; s < c->nshell; ++s)
-        for (int d = 0; d < 3; ++d) shxyz[3 * s + d] = c->xyz[3 * c->sh_atom[s] + d];
-    ShellsDev &sh = c->sh;
-    sh.nshell = c->nshell;
-    sh.natom = c->natom;
-    fsim_status st;
 #define PCHK(expr)                                                                         \
     do {                                                                                   \
         hipError_t e_ = (expr);                                                            \
@@ -332,100 +322,265 @@ extern "C" fsim_status fsim_ctx_create(const fsim_basis *b, const fsim_options *
         if (e_ != hipSuccess)                                                              \
             return cleanup(fail(FSIM_EHIP, std::string(#expr) + ": " + hipGetErrorString(e_))); \
     } while (0)
+#define SCHK(expr)                                                                         \
+    do {                                                                                   \
+        fsim_status s_ = (expr);                                                           \
+        if (s_ != FSIM_OK) return cleanup(s_);                                             \
+    } while (0)
+    HCHK(hipGetDevice(&c->device));
+    c->opt = *o;
+    for (int X = 0; X < NPCLASS; ++X)
+        for (int Y = 0; Y < NPCLASS; ++Y)
+            for (int f = 0; f < 2; ++f) {
+                c->variant[X][Y][f] = ERI_DEFAULT_VARIANT;
+                c->wpb[X][Y][f] = 4;
+                c->tuned_ms[X][Y][f] = 0.0;
+            }
+    c->nmol = nmol;
+    // concatenate the molecules
+    std::vector<int> bf_shell, bf_comp;
+    int gbf = 0;
+    for (int m = 0; m < nmol; ++m) {
+        const fsim_basis *b = &mols[m];
+        const int a0 = c->natom, s0 = c->nshell, p0 = (int)c->exps.size();
+        c->mol_atom0.push_back(a0);
+        c->mol_natom.push_back(b->natom);
+        c->mol_shell0.push_back(s0);
+        c->mol_nshell.push_back(b->nshell);
+        c->mol_bf0.push_back(gbf);
+        c->xyz.insert(c->xyz.end(), b->xyz, b->xyz + 3 * b->natom);
+        c->Z.insert(c->Z.end(), b->Z, b->Z + b->natom);
+        int np = 0;
+        for (int k = 0; k < b->nshell; ++k) np = std::max(np, b->shell_prim0[k] + b->shell_nprim[k]);
+        c->exps.insert(c->exps.end(), b->exps, b->exps + np);
+        c->coefs.insert(c->coefs.end(), b->coefs, b->coefs + np);
+        int nb = 0;
+        for (int k = 0; k < b->nshell; ++k) {
+            c->sh_atom.push_back(a0 + b->shell_atom[k]);
+            c->sh_l.push_back(b->shell_l[k]);
+            c->sh_nprim.push_back(b->shell_nprim[k]);
+            c->sh_prim0.push_back(p0 + b->shell_prim0[k]);
+            c->sh_bf0.push_back(nb);
+            c->sh_mol.push_back(m);
+            for (int q = 0; q < ncart_h(b->shell_l[k]); ++q) {
+                bf_shell.push_back(s0 + k);
+                bf_comp.push_back(q);
+            }
+            nb += ncart_h(b->shell_l[k]);
+        }
+        c->mol_n.push_back(nb);
+        c->mol_nocc.push_back(b->nelec / 2);
+        c->mol_off.push_back(c->packed);
+        c->packed += (long long)nb * nb;
+        c->nmax = std::max(c->nmax, nb);
+        double en = 0.0;
+        for (int A = 0; A < b->natom; ++A)
+            for (int B = 0; B < A; ++B) {
+                const double dx = b->xyz[3 * A] - b->xyz[3 * B], dy = b->xyz[3 * A + 1] - b->xyz[3 * B + 1],
+                             dz = b->xyz[3 * A + 2] - b->xyz[3 * B + 2];
+                en += b->Z[A] * b->Z[B] / std::sqrt(dx * dx + dy * dy + dz * dz);
+            }
+        c->mol_enuc.push_back(en);
+        c->enuc += en;
+        c->natom += b->natom;
+        c->nshell += b->nshell;
+        c->nelec += b->nelec;
+        gbf += nb;
+    }
+    c->nbf = nmol == 1 ? c->mol_n[0] : gbf;
+    c->nocc = c->nelec / 2;
+    const int nprim_tot = (int)c->exps.size();
+    const size_t P = (size_t)c->packed;
+
+    // shells and molecules on the device
+    std::vector<double> shxyz(3 * c->nshell);
+    for (int k = 0; k < c->nshell; ++k)
+        for (int d = 0; d < 3; ++d) shxyz[3 * k + d] = c->xyz[3 * c->sh_atom[k] + d];
+    ShellsDev &sh = c->sh;
+    sh.nshell = c->nshell;
+    sh.natom = c->natom;
+    sh.nmol = nmol;
     PCHK(c->pool.alloc(&sh.xyz, 3 * c->nshell));
     PCHK(c->pool.alloc(&sh.l, c->nshell));
     PCHK(c->pool.alloc(&sh.nprim, c->nshell));
     PCHK(c->pool.alloc(&sh.prim0, c->nshell));
     PCHK(c->pool.alloc(&sh.bf0, c->nshell));
+    PCHK(c->pool.alloc(&sh.mol, c->nshell));
     PCHK(c->pool.alloc(&sh.exps, nprim_tot));
     PCHK(c->pool.alloc(&sh.coef, nprim_tot));
     PCHK(c->pool.alloc(&sh.atom_xyz, 3 * c->natom));
     PCHK(c->pool.alloc(&sh.atom_Z, c->natom));
-    HCHK(hipMemcpy(sh.xyz, shxyz.data(), sizeof(double) * shxyz.size(), hipMemcpyHostToDevice));
-    HCHK(hipMemcpy(sh.l, c->sh_l.data(), sizeof(int) * c->nshell, hipMemcpyHostToDevice));
-    HCHK(hipMemcpy(sh.nprim, c->sh_nprim.data(), sizeof(int) * c->nshell, hipMemcpyHostToDevice));
-    HCHK(hipMemcpy(sh.prim0, c->sh_prim0.data(), sizeof(int) * c->nshell, hipMemcpyHostToDevice));
-    HCHK(hipMemcpy(sh.bf0, c->sh_bf0.data(), sizeof(int) * c->nshell, hipMemcpyHostToDevice));
-    HCHK(hipMemcpy(sh.exps, c->exps.data(), sizeof(double) * nprim_tot, hipMemcpyHostToDevice));
-    HCHK(hipMemcpy(sh.coef, c->coefs.data(), sizeof(double) * nprim_tot, hipMemcpyHostToDevice));
-    HCHK(hipMemcpy(sh.atom_xyz, c->xyz.data(), sizeof(double) * 3 * c->natom, hipMemcpyHostToDevice));
-    HCHK(hipMemcpy(sh.atom_Z, c->Z.data(), sizeof(double) * c->natom, hipMemcpyHostToDevice));
+    PCHK(c->pool.alloc(&sh.mol_atom0, nmol));
+    PCHK(c->pool.alloc(&sh.mol_natom, nmol));
+    PCHK(c->pool.alloc(&sh.mol_bf0, nmol));
+    PCHK(c->pool.alloc(&sh.mol_n, nmol));
+    PCHK(c->pool.alloc(&sh.mol_off, nmol));
+    auto up = [&](void *d, const void *h, size_t bytes) {
+        return hipMemcpy(d, h, bytes, hipMemcpyHostToDevice);
+    };
+    HCHK(up(sh.xyz, shxyz.data(), sizeof(double) * shxyz.size()));
+    HCHK(up(sh.l, c->sh_l.data(), sizeof(int) * c->nshell));
+    HCHK(up(sh.nprim, c->sh_nprim.data(), sizeof(int) * c->nshell));
+    HCHK(up(sh.prim0, c->sh_prim0.data(), sizeof(int) * c->nshell));
+    HCHK(up(sh.bf0, c->sh_bf0.data(), sizeof(int) * c->nshell));
+    HCHK(up(sh.mol, c->sh_mol.data(), sizeof(int) * c->nshell));
+    HCHK(up(sh.exps, c->exps.data(), sizeof(double) * nprim_tot));
+    HCHK(up(sh.coef, c->coefs.data(), sizeof(double) * nprim_tot));
+    HCHK(up(sh.atom_xyz, c->xyz.data(), sizeof(double) * 3 * c->natom));
+    HCHK(up(sh.atom_Z, c->Z.data(), sizeof(double) * c->natom));
+    HCHK(up(sh.mol_atom0, c->mol_atom0.data(), sizeof(int) * nmol));
+    HCHK(up(sh.mol_natom, c->mol_natom.data(), sizeof(int) * nmol));
+    HCHK(up(sh.mol_bf0, c->mol_bf0.data(), sizeof(int) * nmol));
+    HCHK(up(sh.mol_n, c->mol_n.data(), sizeof(int) * nmol));
+    HCHK(up(sh.mol_off, c->mol_off.data(), sizeof(long long) * nmol));
+    c->d_mol_n = sh.mol_n;
+    c->d_mol_off = sh.mol_off;
+    PCHK(c->pool.alloc(&c->d_nocc, nmol));
+    HCHK(up(c->d_nocc, c->mol_nocc.data(), sizeof(int) * nmol));
+    PCHK(c->pool.alloc(&c->Emol, nmol));
     HCHK(launch_shell_norm(sh, nullptr));
     PCHK(c->pool.alloc(&c->boys, (size_t)BOYS_NT * BOYS_NORD));
     HCHK(launch_boys_table(c->boys, nullptr));
 
-    // every shell pair, oriented so that l(s1) >= l(s2)
-    for (int a = 0; a < c->nshell; ++a)
-        for (int bb = 0; bb <= a; ++bb) {
-            int s1 = a, s2 = bb;
-            if (c->sh_l[s1] < c->sh_l[s2]) std::swap(s1, s2);
-            const int pc = pclass(c->sh_l[s1], c->sh_l[s2]);
-            c->pair_lookup[(long long)s1 * c->nshell + s2] = {pc, (int)c->all_s1[pc].size()};
-            c->all_s1[pc].push_back(s1);
-            c->all_s2[pc].push_back(s2);
-        }
-    for (int pc = 0; pc < NPCLASS; ++pc) {
-        st = build_table(c, c->pool, c->all[pc], pc, c->all_s1[pc], c->all_s2[pc]);
-        if (st != FSIM_OK) return cleanup(st);
+    // every shell pair within a molecule, oriented so that l(s1) >= l(s2)
+    for (int m = 0; m < nmol; ++m) {
+        const int s0 = c->mol_shell0[m], ns = c->mol_nshell[m];
+        for (int a = s0; a < s0 + ns; ++a)
+            for (int bb = s0; bb <= a; ++bb) {
+                int s1 = a, s2 = bb;
+                if (c->sh_l[s1] < c->sh_l[s2]) std::swap(s1, s2);
+                const int pc = pclass(c->sh_l[s1], c->sh_l[s2]);
+                c->pair_lookup[(long long)s1 * c->nshell + s2] = {pc, (int)c->all_s1[pc].size()};
+                c->all_s1[pc].push_back(s1);
+                c->all_s2[pc].push_back(s2);
+            }
     }
+    for (int pc = 0; pc < NPCLASS; ++pc)
+        SCHK(build_table(c, c->pool, c->all[pc], pc, c->all_s1[pc], c->all_s2[pc]));
 
-    // work buffers
-    PCHK(c->pool.alloc(&c->S, N2));
-    PCHK(c->pool.alloc(&c->H, N2));
-    PCHK(c->pool.alloc(&c->X, N2));
-    PCHK(c->pool.alloc(&c->Jh, N2));
-    PCHK(c->pool.alloc(&c->Kh, N2));
-    PCHK(c->pool.alloc(&c->F, N2));
-    PCHK(c->pool.alloc(&c->Dn, N2));
-    PCHK(c->pool.alloc(&c->T1, N2));
-    PCHK(c->pool.alloc(&c->T2, N2));
-    PCHK(c->pool.alloc(&c->eig, N));
-    PCHK(c->pool.alloc(&c->ework, N));
+    // packed matrices and Fock work buffers
+    PCHK(c->pool.alloc(&c->S, P));
+    PCHK(c->pool.alloc(&c->H, P));
+    PCHK(c->pool.alloc(&c->X, P));
+    PCHK(c->pool.alloc(&c->Jh, P));
+    PCHK(c->pool.alloc(&c->Kh, P));
+    PCHK(c->pool.alloc(&c->F, P));
+    PCHK(c->pool.alloc(&c->Dn, P));
+    PCHK(c->pool.alloc(&c->T1, P));
+    PCHK(c->pool.alloc(&c->T2, P));
     PCHK(c->pool.alloc(&c->scal, 8));
-    PCHK(c->pool.alloc(&c->dinfo, 4));
+    PCHK(c->pool.alloc(&c->dinfo, std::max(4, nmol)));
     if (rocblas_create_handle(&c->blas) != rocblas_status_success)
         return cleanup(fail(FSIM_EHIP, "rocblas_create_handle failed"));
 
-    // one-electron matrices
+    // one-electron matrices, one packed block per molecule
+    const int Ntot = gbf;
     int *dbs = nullptr, *dbc = nullptr;
-    PCHK(c->pool.alloc(&dbs, N));
-    PCHK(c->pool.alloc(&dbc, N));
-    HCHK(hipMemcpy(dbs, bf_shell.data(), sizeof(int) * N, hipMemcpyHostToDevice));
-    HCHK(hipMemcpy(dbc, bf_comp.data(), sizeof(int) * N, hipMemcpyHostToDevice));
-    HCHK(launch_one_electron_impl(sh, c->boys, N, dbs, dbc, c->S, c->T1, c->T2, nullptr));
-    HCHK(hipMemcpy(c->H, c->T1, sizeof(double) * N2, hipMemcpyDeviceToDevice));
-    if (rocblas_daxpy(c->blas, (int)N2, std::vector<double>{1.0}.data(), c->T2, 1, c->H, 1) !=
-        rocblas_status_success)
-        return cleanup(fail(FSIM_EHIP, "rocblas_daxpy failed"));
+    PCHK(c->pool.alloc(&dbs, Ntot));
+    PCHK(c->pool.alloc(&dbc, Ntot));
+    HCHK(up(dbs, bf_shell.data(), sizeof(int) * Ntot));
+    HCHK(up(dbc, bf_comp.data(), sizeof(int) * Ntot));
+    HCHK(launch_one_electron_impl(sh, c->boys, c->nmax, dbs, dbc, c->S, c->T1, c->T2, nullptr));
+    HCHK(hipMemcpy(c->H, c->T1, sizeof(double) * P, hipMemcpyDeviceToDevice));
+    {
+        const double one = 1.0;
+        if (rocblas_daxpy(c->blas, (int)P, &one, c->T2, 1, c->H, 1) != rocblas_status_success)
+            return cleanup(fail(FSIM_EHIP, "rocblas_daxpy failed"));
+    }
     c->pool.release(dbs);
     c->pool.release(dbc);
 
-    // X = U s^-1/2 U^T
-    HCHK(hipMemcpy(c->T1, c->S, sizeof(double) * N2, hipMemcpyDeviceToDevice));
-    st = syevd(c, c->T1, c->eig, nullptr);
-    if (st != FSIM_OK) return cleanup(st);
-    std::vector<double> sv(N);
-    HCHK(hipMemcpy(sv.data(), c->eig, sizeof(double) * N, hipMemcpyDeviceToHost));
-    if (!(sv[0] > 1e-10))
-        return cleanup(fail(FSIM_EINVAL, "overlap matrix is (near) singular: lowest eigenvalue " +
-                                             std::to_string(sv[0])));
-    HCHK(inv_sqrt(N, c->eig, c->ework, nullptr));
-    HCHK(scale_cols(N, c->T1, c->ework, c->T2, nullptr));
-    st = gemm(c->blas, false, true, N, N, N, 1.0, c->T2, N, c->T1, N, 0.0, c->X, N);
-    if (st != FSIM_OK) return cleanup(st);
-    HCHK(hipDeviceSynchronize());
-
-    const int m = std::max(1, c->opt.diis_m);
-    c->dF.resize(m, nullptr);
-    c->dE.resize(m, nullptr);
-    for (int k = 0; k < m; ++k) {
-        PCHK(c->pool.alloc(&c->dF[k], N2));
-        PCHK(c->pool.alloc(&c->dE[k], N2));
+    const int m_hist = std::max(1, c->opt.diis_m);
+    if (nmol == 1) {
+        const int N = c->nbf;
+        const size_t N2 = (size_t)N * N;
+        PCHK(c->pool.alloc(&c->eig, N));
+        PCHK(c->pool.alloc(&c->ework, N));
+        // X = U s^-1/2 U^T
+        HCHK(hipMemcpy(c->T1, c->S, sizeof(double) * N2, hipMemcpyDeviceToDevice));
+        SCHK(syevd(c, c->T1, c->eig, nullptr));
+        std::vector<double> sv(N);
+        HCHK(hipMemcpy(sv.data(), c->eig, sizeof(double) * N, hipMemcpyDeviceToHost));
+        if (!(sv[0] > 1e-10))
+            return cleanup(fail(FSIM_EINVAL, "overlap matrix is (near) singular: lowest eigenvalue " +
+                                                 std::to_string(sv[0])));
+        HCHK(inv_sqrt(N, c->eig, c->ework, nullptr));
+        HCHK(scale_cols(N, c->T1, c->ework, c->T2, nullptr));
+        SCHK(gemm(c->blas, false, true, N, N, N, 1.0, c->T2, N, c->T1, N, 0.0, c->X, N));
+        c->dF.resize(m_hist, nullptr);
+        c->dE.resize(m_hist, nullptr);
+        for (int k = 0; k < m_hist; ++k) {
+            PCHK(c->pool.alloc(&c->dF[k], N2));
+            PCHK(c->pool.alloc(&c->dE[k], N2));
+        }
+        c->Bm.assign((size_t)m_hist * m_hist, 0.0);
+    } else {
+        const size_t M2 = (size_t)c->nmax * c->nmax, B = M2 * nmol;
+        PCHK(c->pool.alloc(&c->pS, B));
+        PCHK(c->pool.alloc(&c->pX, B));
+        PCHK(c->pool.alloc(&c->pH, B));
+        PCHK(c->pool.alloc(&c->pF, B));
+        PCHK(c->pool.alloc(&c->pD, B));
+        PCHK(c->pool.alloc(&c->pT1, B));
+        PCHK(c->pool.alloc(&c->pT2, B));
+        PCHK(c->pool.alloc(&c->pErr, B));
+        PCHK(c->pool.alloc(&c->pEig, (size_t)c->nmax * nmol));
+        PCHK(c->pool.alloc(&c->ework, (size_t)c->nmax * nmol));
+        PCHK(c->pool.alloc(&c->pRed, (size_t)nmol * (DIIS_MAX + 2)));
+        c->pdF.resize(m_hist, nullptr);
+        c->pdE.resize(m_hist, nullptr);
+        for (int k = 0; k < m_hist; ++k) {
+            PCHK(c->pool.alloc(&c->pdF[k], B));
+            PCHK(c->pool.alloc(&c->pdE[k], B));
+        }
+        c->Bb.assign((size_t)nmol * m_hist * m_hist, 0.0);
+        SCHK(batched_orthogonaliser(c, nullptr));
     }
-    c->Bm.assign((size_t)m * m, 0.0);
+    HCHK(hipDeviceSynchronize());
+    c->Eprev_mol.assign(nmol, 0.0);
+    c->mol_info.assign(nmol, fsim_scf_info{});
+    c->Emol_host.assign(nmol, 0.0);
 #undef PCHK
 #undef HCHK
+#undef SCHK
     *out = c;
+    return FSIM_OK;
+}
+
+extern "C" fsim_status fsim_ctx_create(const fsim_basis *b, const fsim_options *o, fsim_ctx **out) {
+    return create_impl(b, 1, o, out);
+}
+
+extern "C" fsim_status fsim_batch_create(const fsim_basis *mols, int32_t nmol,
+                                         const fsim_options *o, fsim_ctx **out) {
+    return create_impl(mols, nmol, o, out);
+}
+
+// Batched X_m = U_m s_m^-1/2 U_m^T on zero-padded blocks (identity padding).
+static fsim_status batched_orthogonaliser(fsim_ctx *c, hipStream_t s) {
+    const MolLayout L = layout_of(c);
+    const int M = c->nmax;
+    const long long M2 = (long long)M * M;
+    HIPCHK(pad_blocks(L, c->S, c->pS, 1.0, s));
+    HIPCHK(pad_blocks(L, c->H, c->pH, 0.0, s));
+    HIPCHK(hipMemcpyAsync(c->pT1, c->pS, sizeof(double) * M2 * c->nmol, hipMemcpyDeviceToDevice, s));
+    BLASCHK(rocblas_set_stream(c->blas, s));
+    BLASCHK(rocsolver_dsyevd_strided_batched(c->blas, rocblas_evect_original, rocblas_fill_upper, M,
+                                             c->pT1, M, M2, c->pEig, M, c->ework, M, c->dinfo,
+                                             c->nmol));
+    std::vector<double> ev((size_t)M * c->nmol);
+    HIPCHK(hipMemcpy(ev.data(), c->pEig, sizeof(double) * ev.size(), hipMemcpyDeviceToHost));
+    for (int m = 0; m < c->nmol; ++m)
+        if (!(ev[(size_t)m * M] > 1e-10))
+            return fail(FSIM_EINVAL, "molecule " + std::to_string(m) +
+                                         ": overlap matrix is (near) singular");
+    HIPCHK(inv_sqrt(M * c->nmol, c->pEig, c->ework, s));
+    HIPCHK(scale_cols_padded(L, c->pT1, c->ework, c->pT2, s));
+    const double one = 1.0, zero = 0.0;
+    BLASCHK(rocblas_dgemm_strided_batched(c->blas, rocblas_operation_none,
+                                          rocblas_operation_transpose, M, M, M, &one, c->pT2, M,
+                                          M2, c->pT1, M, M2, &zero, c->pX, M, M2, c->nmol));
+    HIPCHK(unpad_blocks(L, c->pX, c->X, s));
     return FSIM_OK;
 }
 
@@ -433,6 +588,11 @@ extern "C" fsim_status fsim_ctx_destroy(fsim_ctx *c) {
     if (!c) return FSIM_OK;
     hipDeviceSynchronize();
     if (c->blas) rocblas_destroy_handle(c->blas);
+    for (int p = 0; p < 2; ++p) {
+        if (c->gexec[p]) hipGraphExecDestroy(c->gexec[p]);
+        if (c->gev[p]) hipEventDestroy(c->gev[p]);
+    }
+    if (c->gstream) hipStreamDestroy(c->gstream);
     for (auto &e : c->ev) hipEventDestroy(e);
     c->screen_pool.clear();
     c->pool.clear();
@@ -456,7 +616,7 @@ extern "C" fsim_status fsim_nuclear_repulsion(const fsim_ctx *c, double *e) {
 extern "C" fsim_status fsim_one_electron(fsim_ctx *c, double *S, double *H, double *X, void *stream) {
     if (!c) return fail(FSIM_EINVAL, "ctx is NULL");
     hipStream_t s = (hipStream_t)stream;
-    const size_t bytes = sizeof(double) * c->nbf * c->nbf;
+    const size_t bytes = sizeof(double) * (size_t)c->packed;
     if (S) HIPCHK(hipMemcpyAsync(S, c->S, bytes, hipMemcpyDeviceToDevice, s));
     if (H) HIPCHK(hipMemcpyAsync(H, c->H, bytes, hipMemcpyDeviceToDevice, s));
     if (X) HIPCHK(hipMemcpyAsync(X, c->X, bytes, hipMemcpyDeviceToDevice, s));
@@ -637,6 +797,7 @@ extern "C" fsim_status fsim_schwarz_screen(fsim_ctx *c, double tau, double tau32
     if (!c) return fail(FSIM_EINVAL, "ctx is NULL");
     if (!(tau >= 0) || !(tau32 >= 0) || !std::isfinite(tau) || !std::isfinite(tau32))
         return fail(FSIM_EINVAL, "thresholds must be finite and >= 0");
+    if (Q_out && c->nmol != 1) return fail(FSIM_EINVAL, "Q_out is only available for one molecule");
     const int ns = c->nshell;
     // diagonal integrals (ab|ab) of every pair
     std::vector<StoreTask> tasks[NPCLASS][NPCLASS];
@@ -662,9 +823,9 @@ extern "C" fsim_status fsim_schwarz_screen(fsim_ctx *c, double tau, double tau32
     std::vector<double> blk(base[NPCLASS]);
     HIPCHK(hipMemcpy(blk.data(), dblk, sizeof(double) * blk.size(), hipMemcpyDeviceToHost));
     hipFree(dblk);
-    c->Qmat.assign((size_t)ns * ns, 0.0);
+    if (c->nmol == 1) c->Qmat.assign((size_t)ns * ns, 0.0);
     std::vector<double> Qpair[NPCLASS];
-    double Qmax = 0.0;
+    std::vector<double> Qmax(c->nmol, 0.0);
     for (int pc = 0; pc < NPCLASS; ++pc) {
         const int n1 = ncart_h(pclass_l1(pc)), n2 = ncart_h(pclass_l2(pc));
         const long long bs = (long long)n1 * n2 * n1 * n2;
@@ -678,39 +839,61 @@ extern "C" fsim_status fsim_schwarz_screen(fsim_ctx *c, double tau, double tau32
                 }
             const double qv = std::sqrt(mx);
             Qpair[pc][i] = qv;
-            Qmax = std::max(Qmax, qv);
             const int s1 = c->all_s1[pc][i], s2 = c->all_s2[pc][i];
-            c->Qmat[(size_t)s1 * ns + s2] = qv;
-            c->Qmat[(size_t)s2 * ns + s1] = qv;
+            Qmax[c->sh_mol[s1]] = std::max(Qmax[c->sh_mol[s1]], qv);
+            if (c->nmol == 1) {
+                c->Qmat[(size_t)s1 * ns + s2] = qv;
+                c->Qmat[(size_t)s2 * ns + s1] = qv;
+            }
         }
     }
-    // kept pairs, sorted by Q (descending; ties by canonical index)
+    // kept pairs per class, ordered by (molecule, Q descending); each
+    // molecule owns a contiguous segment of every class table
+    for (int p = 0; p < 2; ++p)
+        if (c->gexec[p]) {
+            hipGraphExecDestroy(c->gexec[p]);
+            c->gexec[p] = nullptr;
+        }
     c->screen_pool.clear();
     c->screened = false;
     fsim_screen_stats S{};
     for (int pc = 0; pc < NPCLASS; ++pc) S.shell_pairs += c->all[pc].n;
     std::vector<int> order[NPCLASS];
+    std::vector<int> kmol[NPCLASS];                 // molecule of each kept pair
+    std::vector<int> seg[NPCLASS];                  // [nmol + 1] segment starts
     for (int pc = 0; pc < NPCLASS; ++pc) {
+        auto molof = [&](int i) { return c->sh_mol[c->all_s1[pc][i]]; };
         for (int i = 0; i < c->all[pc].n; ++i)
-            if (Qpair[pc][i] * Qmax >= tau) order[pc].push_back(i);
-        std::stable_sort(order[pc].begin(), order[pc].end(),
-                         [&](int a, int b) { return Qpair[pc][a] > Qpair[pc][b]; });
+            if (Qpair[pc][i] * Qmax[molof(i)] >= tau) order[pc].push_back(i);
+        std::stable_sort(order[pc].begin(), order[pc].end(), [&](int a, int b) {
+            const int ma = molof(a), mb = molof(b);
+            if (ma != mb) return ma < mb;
+            return Qpair[pc][a] > Qpair[pc][b];
+        });
         std::vector<int> s1, s2;
         c->Qkept[pc].clear();
+        seg[pc].assign(c->nmol + 1, 0);
         for (int i : order[pc]) {
             s1.push_back(c->all_s1[pc][i]);
             s2.push_back(c->all_s2[pc][i]);
             c->Qkept[pc].push_back(Qpair[pc][i]);
+            kmol[pc].push_back(molof(i));
+            seg[pc][molof(i) + 1]++;
         }
+        for (int m = 0; m < c->nmol; ++m) seg[pc][m + 1] += seg[pc][m];
         STCHK(build_table(c, c->screen_pool, c->kept[pc], pc, s1, s2));
         if (c->kept[pc].n)
             HIPCHK(hipMemcpy(c->kept[pc].Q, c->Qkept[pc].data(), sizeof(double) * c->kept[pc].n,
                              hipMemcpyHostToDevice));
         S.pairs_kept += c->kept[pc].n;
     }
-    // canonical quartet count over all pairs
-    const long long npair = S.shell_pairs;
-    S.quartets_total = npair * (npair + 1) / 2;
+    // canonical quartets: per molecule, npair_m (npair_m + 1) / 2
+    {
+        std::vector<long long> np(c->nmol, 0);
+        for (int pc = 0; pc < NPCLASS; ++pc)
+            for (int i = 0; i < c->all[pc].n; ++i) np[c->sh_mol[c->all_s1[pc][i]]]++;
+        for (int m = 0; m < c->nmol; ++m) S.quartets_total += np[m] * (np[m] + 1) / 2;
+    }
     // work lists
     for (int X = 0; X < NPCLASS; ++X)
         for (int Y = 0; Y <= X; ++Y) {
@@ -720,8 +903,10 @@ extern "C" fsim_status fsim_schwarz_screen(fsim_ctx *c, double tau, double tau32
             const double fpq = flops_per_prim_quartet(la, lb, lc, ld);
             for (int i = 0; i < (int)Qb.size(); ++i) {
                 const double qi = Qb[i];
-                // n = #{j : qi * Qk[j] >= tau}, Qk descending
-                int lo = 0, hi = (int)Qk.size();
+                const int m = kmol[X][i];
+                const int k0 = seg[Y][m], k1 = seg[Y][m + 1];
+                // kets of the same molecule with qi * Q_j >= tau (Q descending)
+                int lo = k0, hi = k1;
                 while (lo < hi) {
                     const int mid = (lo + hi) / 2;
                     if (qi * Qk[mid] >= tau) lo = mid + 1;
@@ -729,34 +914,32 @@ extern "C" fsim_status fsim_schwarz_screen(fsim_ctx *c, double tau, double tau32
                 }
                 int n = lo;
                 if (X == Y) n = std::min(n, i + 1);
-                if (n <= 0) continue;
-                int m = n;
+                if (n <= k0) continue;
+                int split = n;
                 if (tau32 > 0) {
-                    int l2 = 0, h2 = n;
+                    int l2 = k0, h2 = n;
                     while (l2 < h2) {
                         const int mid = (l2 + h2) / 2;
                         if (qi * Qk[mid] >= tau32) l2 = mid + 1;
                         else h2 = mid;
                     }
-                    m = l2;
+                    split = l2;
                 }
                 b64.push_back(i);
-                lo64.push_back(0);
+                lo64.push_back(k0);
                 hi64.push_back(n);
-                if (m > 0) {
+                if (split > k0) {
                     bm64.push_back(i);
-                    lom64.push_back(0);
-                    him64.push_back(m);
+                    lom64.push_back(k0);
+                    him64.push_back(split);
                 }
-                if (n > m) {
+                if (n > split) {
                     bm32.push_back(i);
-                    lom32.push_back(m);
+                    lom32.push_back(split);
                     him32.push_back(n);
                 }
-                // primitive-quartet count and flop model (uniform K per pair here:
-                // take this bra's product count times the kets' average)
-                S.quartets_fp64 += m;
-                S.quartets_fp32 += n - m;
+                S.quartets_fp64 += split - k0;
+                S.quartets_fp32 += n - split;
             }
             ClassLists &cl = c->lists[X][Y];
             STCHK(upload_list(c->screen_pool, cl.all64, b64, lo64, hi64));
@@ -765,13 +948,10 @@ extern "C" fsim_status fsim_schwarz_screen(fsim_ctx *c, double tau, double tau32
             S.quartets_kept += cl.all64.nquartet;
             // primitive quartets: sum over kept quartets of K_bra * K_ket
             std::vector<int> kb(Qb.size()), kk(Qk.size());
-            {
-                std::vector<int> ob = order[X], ok = order[Y];
-                for (size_t i = 0; i < ob.size(); ++i)
-                    kb[i] = c->sh_nprim[c->all_s1[X][ob[i]]] * c->sh_nprim[c->all_s2[X][ob[i]]];
-                for (size_t i = 0; i < ok.size(); ++i)
-                    kk[i] = c->sh_nprim[c->all_s1[Y][ok[i]]] * c->sh_nprim[c->all_s2[Y][ok[i]]];
-            }
+            for (size_t i = 0; i < order[X].size(); ++i)
+                kb[i] = c->sh_nprim[c->all_s1[X][order[X][i]]] * c->sh_nprim[c->all_s2[X][order[X][i]]];
+            for (size_t i = 0; i < order[Y].size(); ++i)
+                kk[i] = c->sh_nprim[c->all_s1[Y][order[Y][i]]] * c->sh_nprim[c->all_s2[Y][order[Y][i]]];
             std::vector<long long> kpre(kk.size() + 1, 0);
             for (size_t j = 0; j < kk.size(); ++j) kpre[j + 1] = kpre[j] + kk[j];
             cl.s64 = cl.sm64 = cl.sm32 = ListStats{};
@@ -816,21 +996,16 @@ extern "C" fsim_status fsim_schwarz_screen(fsim_ctx *c, double tau, double tau32
 // Fock build
 // ---------------------------------------------------------------------------
 
-static fsim_status fock_build(fsim_ctx *c, const double *D, double *F, double *J, double *K,
-                              double *E_elec, fsim_precision prec, hipStream_t s) {
-    if (!c->screened) return fail(FSIM_ESTATE, "fsim_schwarz_screen must run before a Fock build");
-    if (!D) return fail(FSIM_EINVAL, "D must not be NULL");
-    const int N = c->nbf;
-    const size_t N2 = (size_t)N * N;
-    HIPCHK(fill(c->Jh, N2, 0.0, s));
-    HIPCHK(fill(c->Kh, N2, 0.0, s));
-    const bool mixed = prec == FSIM_MIXED && c->tau32 > 0;
-    std::vector<fsim_class_profile> prof;
+// Enqueue the class kernels and the Fock assembly for density D into F (J, K
+// optional) on stream s.  No host synchronisation, no memset: this is the
+// sequence a graph captures.
+static fsim_status enqueue_build(fsim_ctx *c, const double *D, double *F, double *J, double *K,
+                                 bool mixed, std::vector<fsim_class_profile> *prof,
+                                 hipStream_t s) {
+    const size_t P = (size_t)c->packed;
+    HIPCHK(fill(c->Jh, P, 0.0, s));
+    HIPCHK(fill(c->Kh, P, 0.0, s));
     int nev = 0;
-    if (c->profiling && c->ev.empty()) {
-        c->ev.resize(2 * 2 * NPCLASS * NPCLASS);
-        for (auto &e : c->ev) HIPCHK(hipEventCreate(&e));
-    }
     // heaviest classes (highest L) first
     for (int X = NPCLASS - 1; X >= 0; --X)
         for (int Y = X; Y >= 0; --Y) {
@@ -838,7 +1013,7 @@ static fsim_status fock_build(fsim_ctx *c, const double *D, double *F, double *J
             for (int part = 0; part < (mixed ? 2 : 1); ++part) {
                 const TileList &tl = mixed ? (part == 0 ? cl.mix64 : cl.mix32) : cl.all64;
                 if (tl.ntile == 0) continue;
-                if (c->profiling) {
+                if (prof) {
                     const ListStats &ls = mixed ? (part == 0 ? cl.sm64 : cl.sm32) : cl.s64;
                     fsim_class_profile pr{};
                     pr.bra_class = X;
@@ -848,7 +1023,7 @@ static fsim_status fock_build(fsim_ctx *c, const double *D, double *F, double *J
                     pr.quartets = ls.nq;
                     pr.prim_quartets = ls.npq;
                     pr.flops = ls.flops;
-                    prof.push_back(pr);
+                    prof->push_back(pr);
                     HIPCHK(hipEventRecord(c->ev[nev++], s));
                 }
                 EriArgs a{};
@@ -859,29 +1034,84 @@ static fsim_status fock_build(fsim_ctx *c, const double *D, double *F, double *J
                 a.D = D;
                 a.Jh = c->Jh;
                 a.Kh = c->Kh;
-                a.nbf = N;
+                a.nbf = c->nbf;
+                a.mol_off = c->d_mol_off;
+                a.mol_n = c->d_mol_n;
                 a.boys = c->boys;
                 const int f32 = mixed && part == 1;
                 HIPCHK(launch_eri(X, Y, f32, false, c->variant[X][Y][f32], c->wpb[X][Y][f32], a, s));
-                if (c->profiling) HIPCHK(hipEventRecord(c->ev[nev++], s));
+                if (prof) HIPCHK(hipEventRecord(c->ev[nev++], s));
             }
         }
-    HIPCHK(assemble_fock(N, c->Jh, c->Kh, c->H, F, J, K, s));
-    if (c->profiling) {
-        HIPCHK(hipStreamSynchronize(s));
-        for (size_t k = 0; k < prof.size(); ++k) {
-            float ms = 0.f;
-            HIPCHK(hipEventElapsedTime(&ms, c->ev[2 * k], c->ev[2 * k + 1]));
-            prof[k].ms = ms;
+    HIPCHK(assemble_fock_packed(layout_of(c), c->Jh, c->Kh, c->H, F, J, K, s));
+    return FSIM_OK;
+}
+
+static fsim_status fock_build(fsim_ctx *c, const double *D, double *F, double *J, double *K,
+                              double *E_elec, fsim_precision prec, hipStream_t s) {
+    if (!c->screened) return fail(FSIM_ESTATE, "fsim_schwarz_screen must run before a Fock build");
+    if (!D) return fail(FSIM_EINVAL, "D must not be NULL");
+    const size_t P = (size_t)c->packed;
+    const bool mixed = prec == FSIM_MIXED && c->tau32 > 0;
+    if (c->profiling && c->ev.empty()) {
+        c->ev.resize(2 * 2 * NPCLASS * NPCLASS);
+        for (auto &e : c->ev) HIPCHK(hipEventCreate(&e));
+    }
+    const bool use_graph = c->graph_enabled && !c->profiling && !J && !K && F;
+    if (use_graph) {
+        const int g = mixed ? 1 : 0;
+        if (!c->gstream) {
+            HIPCHK(hipStreamCreateWithFlags(&c->gstream, hipStreamNonBlocking));
+            for (auto &e : c->gev) HIPCHK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+            HIPCHK(c->pool.alloc(&c->gD, P));
+            HIPCHK(c->pool.alloc(&c->gF, P));
         }
-        c->prof = prof;
+        // order the internal stream after the caller's work
+        HIPCHK(hipEventRecord(c->gev[0], s));
+        HIPCHK(hipStreamWaitEvent(c->gstream, c->gev[0], 0));
+        HIPCHK(hipMemcpyAsync(c->gD, D, sizeof(double) * P, hipMemcpyDeviceToDevice, c->gstream));
+        if (!c->gexec[g]) {
+            hipGraph_t graph = nullptr;
+            HIPCHK(hipStreamBeginCapture(c->gstream, hipStreamCaptureModeThreadLocal));
+            fsim_status st = enqueue_build(c, c->gD, c->gF, nullptr, nullptr, mixed, nullptr,
+                                           c->gstream);
+            hipError_t ec = hipStreamEndCapture(c->gstream, &graph);
+            if (st != FSIM_OK) {
+                if (graph) hipGraphDestroy(graph);
+                return st;
+            }
+            HIPCHK(ec);
+            hipError_t ei = hipGraphInstantiate(&c->gexec[g], graph, nullptr, nullptr, 0);
+            hipGraphDestroy(graph);
+            HIPCHK(ei);
+        }
+        HIPCHK(hipGraphLaunch(c->gexec[g], c->gstream));
+        HIPCHK(hipMemcpyAsync(F, c->gF, sizeof(double) * P, hipMemcpyDeviceToDevice, c->gstream));
+        HIPCHK(hipEventRecord(c->gev[1], c->gstream));
+        HIPCHK(hipStreamWaitEvent(s, c->gev[1], 0));
+    } else {
+        std::vector<fsim_class_profile> prof;
+        STCHK(enqueue_build(c, D, F, J, K, mixed, c->profiling ? &prof : nullptr, s));
+        if (c->profiling) {
+            HIPCHK(hipStreamSynchronize(s));
+            for (size_t k = 0; k < prof.size(); ++k) {
+                float ms = 0.f;
+                HIPCHK(hipEventElapsedTime(&ms, c->ev[2 * k], c->ev[2 * k + 1]));
+                prof[k].ms = ms;
+            }
+            c->prof = prof;
+        }
     }
     if (E_elec) {
         if (!F) return fail(FSIM_EINVAL, "E_elec needs F");
-        HIPCHK(fill(c->scal, 1, 0.0, s));
-        HIPCHK(dot3(N2, D, c->H, F, 0.5, c->scal, s));
-        HIPCHK(hipMemcpyAsync(E_elec, c->scal, sizeof(double), hipMemcpyDeviceToHost, s));
+        HIPCHK(fill(c->Emol, c->nmol, 0.0, s));
+        HIPCHK(dot3_packed(layout_of(c), D, c->H, F, 0.5, c->Emol, s));
+        HIPCHK(hipMemcpyAsync(c->Emol_host.data(), c->Emol, sizeof(double) * c->nmol,
+                              hipMemcpyDeviceToHost, s));
         HIPCHK(hipStreamSynchronize(s));
+        double e = 0.0;
+        for (double v : c->Emol_host) e += v;
+        *E_elec = e;
     }
     return FSIM_OK;
 }
@@ -1013,9 +1243,17 @@ extern "C" fsim_status fsim_autotune(fsim_ctx *c, const double *D, fsim_precisio
     return st;
 }
 
+static fsim_status batched_density(fsim_ctx *c, const double *Fin, double *Dpad, hipStream_t s);
+
 extern "C" fsim_status fsim_core_guess(fsim_ctx *c, double *D, void *stream) {
     if (!c || !D) return fail(FSIM_EINVAL, "NULL argument");
     hipStream_t s = (hipStream_t)stream;
+    if (c->nmol > 1) {
+        STCHK(batched_density(c, c->pH, c->pD, s));
+        HIPCHK(unpad_blocks(layout_of(c), c->pD, D, s));
+        HIPCHK(hipStreamSynchronize(s));
+        return FSIM_OK;
+    }
     STCHK(density_from_fock(c, c->H, D, s));
     HIPCHK(hipStreamSynchronize(s));
     return FSIM_OK;
@@ -1026,6 +1264,8 @@ extern "C" fsim_status fsim_scf_reset(fsim_ctx *c) {
     c->diis_count = 0;
     c->diis_next = 0;
     std::fill(c->Bm.begin(), c->Bm.end(), 0.0);
+    std::fill(c->Bb.begin(), c->Bb.end(), 0.0);
+    for (auto &r : c->mol_info) r = fsim_scf_info{};
     c->iter = 0;
     c->have_prev = false;
     return FSIM_OK;
@@ -1074,10 +1314,14 @@ static bool diis_solve(const std::vector<double> &B, int m, const std::vector<in
     return true;
 }
 
+static fsim_status batched_scf_step(fsim_ctx *c, double *D, fsim_scf_info *info,
+                                    fsim_precision prec, hipStream_t s);
+
 extern "C" fsim_status fsim_scf_step(fsim_ctx *c, double *D, fsim_scf_info *info,
                                      fsim_precision prec, void *stream) {
     if (!c || !D || !info) return fail(FSIM_EINVAL, "NULL argument");
     hipStream_t s = (hipStream_t)stream;
+    if (c->nmol > 1) return batched_scf_step(c, D, info, prec, s);
     const int N = c->nbf;
     const size_t N2 = (size_t)N * N;
     double Eel = 0.0;
@@ -1142,5 +1386,162 @@ extern "C" fsim_status fsim_scf_step(fsim_ctx *c, double *D, fsim_scf_info *info
                       (c->opt.conv_dE <= 0 || (c->have_prev && std::fabs(info->dE) < c->opt.conv_dE));
     c->have_prev = true;
     c->E_prev = Etot;
+    return FSIM_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Batched SCF (many molecules): zero-padded N_max blocks, strided-batched
+// rocBLAS / rocSOLVER, DIIS per molecule.  The padding of X^T F X gets a
+// large distinct diagonal, so its eigenvectors are never occupied and the
+// real block's eigenproblem decouples exactly.
+// ---------------------------------------------------------------------------
+static fsim_status bgemm(fsim_ctx *c, bool ta, bool tb, int k, double alpha, const double *A,
+                         const double *B, double beta, double *C) {
+    const int M = c->nmax;
+    const long long M2 = (long long)M * M;
+    BLASCHK(rocblas_dgemm_strided_batched(
+        c->blas, ta ? rocblas_operation_transpose : rocblas_operation_none,
+        tb ? rocblas_operation_transpose : rocblas_operation_none, M, M, k, &alpha, A, M, M2, B, M,
+        M2, &beta, C, M, M2, c->nmol));
+    return FSIM_OK;
+}
+
+// Dpad = 2 C_occ C_occ^T with C = X V, V the eigenvectors of X^T Fin X
+// (padded blocks).  Dpad may alias Fin; scratch pT1, pT2.
+static fsim_status batched_density(fsim_ctx *c, const double *Fin, double *Dpad, hipStream_t s) {
+    const MolLayout L = layout_of(c);
+    const int M = c->nmax;
+    const long long M2 = (long long)M * M;
+    BLASCHK(rocblas_set_stream(c->blas, s));
+    STCHK(bgemm(c, false, false, M, 1.0, Fin, c->pX, 0.0, c->pT1));      // F X
+    STCHK(bgemm(c, true, false, M, 1.0, c->pX, c->pT1, 0.0, c->pT2));    // X^T F X
+    HIPCHK(pad_diag(L, c->pT2, 1e3, s));
+    BLASCHK(rocsolver_dsyevd_strided_batched(c->blas, rocblas_evect_original, rocblas_fill_upper, M,
+                                             c->pT2, M, M2, c->pEig, M, c->ework, M, c->dinfo,
+                                             c->nmol));
+    STCHK(bgemm(c, false, false, M, 1.0, c->pX, c->pT2, 0.0, c->pT1));   // C = X V
+    HIPCHK(mask_cols(L, c->d_nocc, c->pT1, s));
+    STCHK(bgemm(c, false, true, M, 2.0, c->pT1, c->pT1, 0.0, Dpad));
+    return FSIM_OK;
+}
+
+static fsim_status batched_scf_step(fsim_ctx *c, double *D, fsim_scf_info *info,
+                                    fsim_precision prec, hipStream_t s) {
+    const MolLayout L = layout_of(c);
+    const int nm = c->nmol;
+    double Etot_el = 0.0;
+    STCHK(fock_build(c, D, c->F, nullptr, nullptr, &Etot_el, prec, s));
+    HIPCHK(pad_blocks(L, c->F, c->pF, 0.0, s));
+    HIPCHK(pad_blocks(L, D, c->pD, 0.0, s));
+    BLASCHK(rocblas_set_stream(c->blas, s));
+    // e = F D S - S D F per molecule
+    STCHK(bgemm(c, false, false, c->nmax, 1.0, c->pF, c->pD, 0.0, c->pT1));
+    STCHK(bgemm(c, false, false, c->nmax, 1.0, c->pT1, c->pS, 0.0, c->pT2));
+    const int mh = (int)c->pdF.size();
+    const int slot = c->diis_next;
+    HIPCHK(antisym_padded(L, c->pT2, c->pdE[slot], s));
+    HIPCHK(hipMemcpyAsync(c->pdF[slot], c->pF, sizeof(double) * (size_t)c->nmax * c->nmax * nm,
+                          hipMemcpyDeviceToDevice, s));
+    c->diis_next = (slot + 1) % mh;
+    c->diis_count = std::min(c->diis_count + 1, mh);
+    const int cnt = c->diis_count;
+    std::vector<int> slots;
+    for (int k = 0; k < cnt; ++k) slots.push_back((slot - k + mh) % mh);
+    DiisPtrs H{};
+    for (int k = 0; k < cnt; ++k) H.m[k] = c->pdE[slots[k]];
+    HIPCHK(fill(c->pRed, (size_t)nm * cnt, 0.0, s));
+    HIPCHK(dots_padded(L, c->pdE[slot], H, cnt, c->pRed, s));
+    std::vector<double> dots((size_t)nm * cnt);
+    HIPCHK(hipMemcpyAsync(dots.data(), c->pRed, sizeof(double) * dots.size(), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    std::vector<double> coef((size_t)nm * cnt, 0.0), comm(nm, 0.0);
+    std::vector<int> used(nm, 0);
+    for (int m = 0; m < nm; ++m) {
+        double *Bmol = c->Bb.data() + (size_t)m * mh * mh;
+        for (int k = 0; k < cnt; ++k) {
+            Bmol[(size_t)slot * mh + slots[k]] = dots[(size_t)m * cnt + k];
+            Bmol[(size_t)slots[k] * mh + slot] = dots[(size_t)m * cnt + k];
+        }
+        comm[m] = std::sqrt(std::max(0.0, Bmol[(size_t)slot * mh + slot]));
+        coef[(size_t)m * cnt + 0] = 1.0;   // plain F unless DIIS applies
+        if (c->opt.diis_m > 0 && cnt >= 2) {
+            std::vector<double> Bv(Bmol, Bmol + (size_t)mh * mh), cv;
+            if (diis_solve(Bv, cnt, slots, mh, cv)) {
+                for (int k = 0; k < cnt; ++k) coef[(size_t)m * cnt + k] = cv[k];
+                used[m] = 1;
+            }
+        }
+    }
+    DiisPtrs Fh{};
+    for (int k = 0; k < cnt; ++k) Fh.m[k] = c->pdF[slots[k]];
+    HIPCHK(hipMemcpyAsync(c->pRed, coef.data(), sizeof(double) * coef.size(), hipMemcpyHostToDevice, s));
+    HIPCHK(lincomb_padded(L, Fh, cnt, c->pRed, c->pErr, s));
+    STCHK(batched_density(c, c->pErr, c->pErr, s));          // new padded density in pErr
+    HIPCHK(fill(c->pRed, nm, 0.0, s));
+    HIPCHK(diff2_padded(L, c->pErr, c->pD, c->pRed, s));
+    std::vector<double> d2(nm);
+    HIPCHK(hipMemcpyAsync(d2.data(), c->pRed, sizeof(double) * nm, hipMemcpyDeviceToHost, s));
+    HIPCHK(unpad_blocks(L, c->pErr, D, s));
+    HIPCHK(hipStreamSynchronize(s));
+    c->iter += 1;
+    fsim_scf_info agg{};
+    agg.iter = c->iter;
+    agg.converged = 1;
+    for (int m = 0; m < nm; ++m) {
+        fsim_scf_info &r = c->mol_info[m];
+        const double E = c->Emol_host[m] + c->mol_enuc[m];
+        r.E_elec = c->Emol_host[m];
+        r.dE = c->have_prev ? E - c->Eprev_mol[m] : 0.0;
+        r.E_total = E;
+        r.rms_dD = std::sqrt(d2[m]) / c->mol_n[m];
+        r.comm_norm = comm[m];
+        r.iter = c->iter;
+        r.diis_used = used[m];
+        r.converged = r.rms_dD < c->opt.conv_rms_dD &&
+                      (c->opt.conv_dE <= 0 || (c->have_prev && std::fabs(r.dE) < c->opt.conv_dE));
+        c->Eprev_mol[m] = E;
+        agg.E_total += E;
+        agg.E_elec += r.E_elec;
+        agg.dE += r.dE;
+        agg.rms_dD = std::max(agg.rms_dD, r.rms_dD);
+        agg.comm_norm = std::max(agg.comm_norm, r.comm_norm);
+        agg.diis_used += r.diis_used;
+        agg.converged = agg.converged && r.converged;
+    }
+    c->have_prev = true;
+    c->E_prev = agg.E_total;
+    *info = agg;
+    return FSIM_OK;
+}
+
+extern "C" fsim_status fsim_batch_layout(const fsim_ctx *c, int32_t *nmol, int32_t *nbf,
+                                         int64_t *offsets, double *enuc, int64_t *packed) {
+    if (!c) return fail(FSIM_EINVAL, "ctx is NULL");
+    if (nmol) *nmol = c->nmol;
+    for (int m = 0; m < c->nmol; ++m) {
+        if (nbf) nbf[m] = c->mol_n[m];
+        if (offsets) offsets[m] = c->mol_off[m];
+        if (enuc) enuc[m] = c->mol_enuc[m];
+    }
+    if (packed) *packed = c->packed;
+    return FSIM_OK;
+}
+
+extern "C" fsim_status fsim_batch_energies(const fsim_ctx *c, double *E_elec) {
+    if (!c || !E_elec) return fail(FSIM_EINVAL, "NULL argument");
+    for (int m = 0; m < c->nmol; ++m) E_elec[m] = c->Emol_host[m];
+    return FSIM_OK;
+}
+
+extern "C" fsim_status fsim_batch_scf_info(const fsim_ctx *c, fsim_scf_info *info) {
+    if (!c || !info) return fail(FSIM_EINVAL, "NULL argument");
+    if (c->nmol == 1) return fail(FSIM_ESTATE, "not a batched context");
+    for (int m = 0; m < c->nmol; ++m) info[m] = c->mol_info[m];
+    return FSIM_OK;
+}
+
+extern "C" fsim_status fsim_set_graph(fsim_ctx *c, int32_t enable) {
+    if (!c) return fail(FSIM_EINVAL, "ctx is NULL");
+    c->graph_enabled = enable != 0;
     return FSIM_OK;
 }

@@ -162,8 +162,6 @@ __global__ __launch_bounds__(256) void k_eri_lane(EriArgs a) {
     const T *__restrict__ Eb = etab<T>(a.bra);
     const T *__restrict__ Ek = etab<T>(a.ket);
     const size_t nb = a.bra.n, nk = a.ket.n;
-    const int N = a.nbf;
-    const double *__restrict__ D = a.D;
 
     for (int tile0 = blockIdx.x * wpb + (threadIdx.x >> 6); tile0 < ntile;
          tile0 += gridDim.x * wpb) {
@@ -185,6 +183,13 @@ __global__ __launch_bounds__(256) void k_eri_lane(EriArgs a) {
         }
         const int nbp = __builtin_amdgcn_readfirstlane(a.bra.nprim[bra]);
         const int nkp = active ? a.ket.nprim[ket] : 0;
+        // the quartet's molecule block (bra and ket pairs share the molecule)
+        const int mol = __builtin_amdgcn_readfirstlane(a.bra.mol[bra]);
+        const long long mbase = STORE ? 0 : a.mol_off[mol];
+        const int N = STORE ? 0 : a.mol_n[mol];
+        const double *__restrict__ D = STORE ? nullptr : a.D + mbase;
+        double *__restrict__ Jh = STORE ? nullptr : a.Jh + mbase;
+        double *__restrict__ Kh = STORE ? nullptr : a.Kh + mbase;
         int f1 = 0, f2 = 0, f3 = 0, f4 = 0;
         double fac = 0.0;
         long long soff = 0;
@@ -327,7 +332,7 @@ __global__ __launch_bounds__(256) void k_eri_lane(EriArgs a) {
                         sum += (double)out[abl][cdl] * D[(size_t)(f3 + ic) * N + f4 + id];
                     });
                     sum = wave_sum(2.0 * fac * sum);
-                    if (lane == 0) atomicAdd(&a.Jh[(size_t)(f1 + ia) * N + f2 + ib], sum);
+                    if (lane == 0) atomicAdd(&Jh[(size_t)(f1 + ia) * N + f2 + ib], sum);
                 });
                 if (active) {
                     // J'_cd (partial over this chunk's a)
@@ -340,7 +345,7 @@ __global__ __launch_bounds__(256) void k_eri_lane(EriArgs a) {
                             constexpr int ia = A0 + abl / NB, ib = abl % NB;
                             sum += (double)out[abl][cdl] * D[(size_t)(f1 + ia) * N + f2 + ib];
                         });
-                        atomicAdd(&a.Jh[(size_t)(f3 + ic) * N + f4 + id], 2.0 * fac * sum);
+                        atomicAdd(&Jh[(size_t)(f3 + ic) * N + f4 + id], 2.0 * fac * sum);
                     });
                     // K'_xc for x in {a (with D_bd), b (with D_ad)} and every c in the chunk
                     static_for<NC>([&](auto c_) {
@@ -360,7 +365,7 @@ __global__ __launch_bounds__(256) void k_eri_lane(EriArgs a) {
                                                    D[(size_t)(f2 + ib) * N + f4 + id];
                                     });
                                 });
-                                atomicAdd(&a.Kh[(size_t)(f1 + A0 + al) * N + f3 + ic], fac * sum);
+                                atomicAdd(&Kh[(size_t)(f1 + A0 + al) * N + f3 + ic], fac * sum);
                             });
                             static_for<NB>([&](auto b_) {
                                 constexpr int ib = decltype(b_)::value;
@@ -375,7 +380,7 @@ __global__ __launch_bounds__(256) void k_eri_lane(EriArgs a) {
                                                    D[(size_t)(f1 + A0 + al) * N + f4 + id];
                                     });
                                 });
-                                atomicAdd(&a.Kh[(size_t)(f2 + ib) * N + f3 + ic], fac * sum);
+                                atomicAdd(&Kh[(size_t)(f2 + ib) * N + f3 + ic], fac * sum);
                             });
                         }
                     });
@@ -401,7 +406,7 @@ __global__ __launch_bounds__(256) void k_eri_lane(EriArgs a) {
                                                    D[(size_t)(f2 + ib) * N + f3 + ic];
                                     });
                                 });
-                                atomicAdd(&a.Kh[(size_t)(f1 + A0 + al) * N + f4 + id], fac * sum);
+                                atomicAdd(&Kh[(size_t)(f1 + A0 + al) * N + f4 + id], fac * sum);
                             });
                             static_for<NB>([&](auto b_) {
                                 constexpr int ib = decltype(b_)::value;
@@ -416,7 +421,7 @@ __global__ __launch_bounds__(256) void k_eri_lane(EriArgs a) {
                                                    D[(size_t)(f1 + A0 + al) * N + f3 + ic];
                                     });
                                 });
-                                atomicAdd(&a.Kh[(size_t)(f2 + ib) * N + f4 + id], fac * sum);
+                                atomicAdd(&Kh[(size_t)(f2 + ib) * N + f4 + id], fac * sum);
                             });
                         }
                     });
@@ -616,26 +621,30 @@ __global__ __launch_bounds__(64) void k_eri_wave(EriArgs a) {
                     }
                 }
             } else {
-                const int N = a.nbf;
+                const int mol = a.bra.mol[bra];
+                const long long mbase = a.mol_off[mol];
+                const int N = a.mol_n[mol];
+                const double *__restrict__ D = a.D + mbase;
+                double *__restrict__ Jh = a.Jh + mbase;
+                double *__restrict__ Kh = a.Kh + mbase;
                 const int f1 = a.bra.bf1[bra], f2 = a.bra.bf2[bra];
                 const int f3 = a.ket.bf1[ket], f4 = a.ket.bf2[ket];
                 double fac = 1.0;
                 if (a.bra.sh1[bra] == a.bra.sh2[bra]) fac *= 0.5;
                 if (a.ket.sh1[ket] == a.ket.sh2[ket]) fac *= 0.5;
                 if (a.same_class && ket == bra) fac *= 0.5;
-                const double *__restrict__ D = a.D;
 #pragma unroll
                 for (int k = 0; k < NOL; ++k) {
                     if (lane + 64 * k < NO) {
                         const size_t I = f1 + oab[k] / NB, J = f2 + oab[k] % NB,
                                      K = f3 + ocd[k] / ND, M = f4 + ocd[k] % ND;
                         const double v = fac * (double)o[k];
-                        atomicAdd(&a.Jh[I * N + J], 2.0 * v * D[K * N + M]);
-                        atomicAdd(&a.Jh[K * N + M], 2.0 * v * D[I * N + J]);
-                        atomicAdd(&a.Kh[I * N + K], v * D[J * N + M]);
-                        atomicAdd(&a.Kh[J * N + K], v * D[I * N + M]);
-                        atomicAdd(&a.Kh[I * N + M], v * D[J * N + K]);
-                        atomicAdd(&a.Kh[J * N + M], v * D[I * N + K]);
+                        atomicAdd(&Jh[I * N + J], 2.0 * v * D[K * N + M]);
+                        atomicAdd(&Jh[K * N + M], 2.0 * v * D[I * N + J]);
+                        atomicAdd(&Kh[I * N + K], v * D[J * N + M]);
+                        atomicAdd(&Kh[J * N + K], v * D[I * N + M]);
+                        atomicAdd(&Kh[I * N + M], v * D[J * N + K]);
+                        atomicAdd(&Kh[J * N + M], v * D[I * N + K]);
                     }
                 }
             }

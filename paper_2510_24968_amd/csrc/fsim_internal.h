@@ -115,7 +115,8 @@ struct PairTable {
     int ne = 0;       // box entries per primitive pair
     int l1 = 0, l2 = 0;
     int *sh1 = nullptr, *sh2 = nullptr;   // shell indices (l(sh1) >= l(sh2))
-    int *bf1 = nullptr, *bf2 = nullptr;   // first basis function of each shell
+    int *bf1 = nullptr, *bf2 = nullptr;   // first basis function of each shell (in its molecule)
+    int *mol = nullptr;                   // molecule of the pair (batched contexts)
     int *nprim = nullptr;                 // primitive pairs in use
     double *Q = nullptr;                  // Schwarz factor
     double *p = nullptr;                  // [kmax][n]
@@ -143,10 +144,12 @@ struct EriArgs {
     int same_class;
     // Fock mode
     TileList tl;
-    const double *D;
+    const double *D;        // packed per-molecule blocks (one block for a single molecule)
     double *Jh;
     double *Kh;
     int nbf;
+    const long long *mol_off;   // [nmol] offset of each molecule's N_m x N_m block
+    const int *mol_n;           // [nmol] N_m
     // store mode: tile t has bra st_bra[t]; lane l evaluates ket st_ket[t*64+l]
     // (-1 = idle) and writes component (i,j,k,l) to
     // out[st_off + i*s0 + j*s1 + k*s2 + l*s3]
@@ -163,9 +166,15 @@ struct EriArgs {
 // setup kernels (setup.hip)
 hipError_t launch_boys_table(double *tab, hipStream_t s);
 struct ShellsDev {
-    int nshell = 0, natom = 0;
+    int nshell = 0, natom = 0, nmol = 1;
     double *xyz = nullptr;     // [nshell][3] centre of each shell
-    int *l = nullptr, *nprim = nullptr, *prim0 = nullptr, *bf0 = nullptr;
+    int *l = nullptr, *nprim = nullptr, *prim0 = nullptr;
+    int *bf0 = nullptr;        // first basis function of the shell within its molecule
+    int *mol = nullptr;        // molecule of the shell
+    int *mol_atom0 = nullptr, *mol_natom = nullptr;   // [nmol] atom range
+    int *mol_bf0 = nullptr;    // [nmol] first global basis function
+    int *mol_n = nullptr;      // [nmol] N_m
+    long long *mol_off = nullptr;   // [nmol] packed block offset
     double *exps = nullptr;
     double *coef = nullptr;    // normalised (radial norm x contraction renorm)
     double *atom_xyz = nullptr;
@@ -174,7 +183,7 @@ struct ShellsDev {
 hipError_t launch_shell_norm(const ShellsDev &sh, hipStream_t s);
 hipError_t launch_build_pairs(const ShellsDev &sh, PairTable &t, const int *pair_sh1,
                               const int *pair_sh2, hipStream_t s);
-hipError_t launch_one_electron_impl(const ShellsDev &sh, const double *boys, int nbf,
+hipError_t launch_one_electron_impl(const ShellsDev &sh, const double *boys, int nmax,
                                     const int *bf_shell, const int *bf_comp, double *S,
                                     double *T, double *V, hipStream_t s);
 // quartet-class dispatch (eri_dispatch.hip); bra_pc >= ket_pc

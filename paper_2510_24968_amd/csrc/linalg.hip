@@ -95,6 +95,229 @@ __global__ void k_lincomb(size_t n, int m, DiisPtrs P, double *out) {
     }
 }
 
+// ---------------------------------------------------------------------------
+// packed / padded per-molecule kernels: grid.y runs over molecules
+// ---------------------------------------------------------------------------
+__global__ void k_assemble_packed(MolLayout L, const double *__restrict__ Jh,
+                                  const double *__restrict__ Kh, const double *__restrict__ H,
+                                  double *F, double *J, double *K) {
+    const int m = blockIdx.y, n = L.n[m];
+    const size_t base = L.off[m], n2 = (size_t)n * n;
+    for (size_t x = blockIdx.x * (size_t)blockDim.x + threadIdx.x; x < n2;
+         x += (size_t)gridDim.x * blockDim.x) {
+        const size_t i = x / n, j = x - i * n;
+        const size_t a = base + x, at = base + j * n + i;
+        const double jj = Jh[a] + Jh[at], kk = Kh[a] + Kh[at];
+        if (F) F[a] = H[a] + jj - 0.5 * kk;
+        if (J) J[a] = jj;
+        if (K) K[a] = kk;
+    }
+}
+
+__global__ void k_dot3_packed(MolLayout L, const double *__restrict__ A,
+                              const double *__restrict__ B, const double *__restrict__ C, double w,
+                              double *E) {
+    __shared__ double red[256];
+    const int m = blockIdx.y, n = L.n[m];
+    const size_t base = L.off[m], n2 = (size_t)n * n;
+    double acc = 0.0;
+    for (size_t x = blockIdx.x * (size_t)blockDim.x + threadIdx.x; x < n2;
+         x += (size_t)gridDim.x * blockDim.x)
+        acc += A[base + x] * (B[base + x] + (C ? C[base + x] : 0.0));
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int o = blockDim.x / 2; o > 0; o >>= 1) {
+        if ((int)threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) atomicAdd(&E[m], w * red[0]);
+}
+
+__global__ void k_pad(MolLayout L, const double *__restrict__ packed, double *padded, double diag) {
+    const int m = blockIdx.y, n = L.n[m], M = L.nmax;
+    const size_t M2 = (size_t)M * M;
+    for (size_t x = blockIdx.x * (size_t)blockDim.x + threadIdx.x; x < M2;
+         x += (size_t)gridDim.x * blockDim.x) {
+        const int i = (int)(x / M), j = (int)(x - (size_t)i * M);
+        double v;
+        if (i < n && j < n) v = packed[L.off[m] + (size_t)i * n + j];
+        else v = (i == j) ? diag : 0.0;
+        padded[(size_t)m * M2 + x] = v;
+    }
+}
+
+__global__ void k_unpad(MolLayout L, const double *__restrict__ padded, double *packed) {
+    const int m = blockIdx.y, n = L.n[m], M = L.nmax;
+    const size_t n2 = (size_t)n * n;
+    for (size_t x = blockIdx.x * (size_t)blockDim.x + threadIdx.x; x < n2;
+         x += (size_t)gridDim.x * blockDim.x) {
+        const size_t i = x / n, j = x - i * n;
+        packed[L.off[m] + x] = padded[(size_t)m * M * M + i * M + j];
+    }
+}
+
+__global__ void k_pad_diag(MolLayout L, double *padded, double big) {
+    const int m = blockIdx.y, n = L.n[m], M = L.nmax;
+    const size_t M2 = (size_t)M * M;
+    for (size_t x = blockIdx.x * (size_t)blockDim.x + threadIdx.x; x < M2;
+         x += (size_t)gridDim.x * blockDim.x) {
+        const int i = (int)(x / M), j = (int)(x - (size_t)i * M);
+        if (i >= n || j >= n) padded[(size_t)m * M2 + x] = (i == j) ? big * (1.0 + i) : 0.0;
+    }
+}
+
+__global__ void k_mask_cols(MolLayout L, const int *__restrict__ nocc, double *C) {
+    const int m = blockIdx.y, M = L.nmax;
+    const size_t M2 = (size_t)M * M;
+    for (size_t x = blockIdx.x * (size_t)blockDim.x + threadIdx.x; x < M2;
+         x += (size_t)gridDim.x * blockDim.x) {
+        const int col = (int)(x / M);   // column-major: column index is the slow one
+        if (col >= nocc[m]) C[(size_t)m * M2 + x] = 0.0;
+    }
+}
+
+__global__ void k_antisym_padded(MolLayout L, const double *__restrict__ A, double *E) {
+    const int m = blockIdx.y, M = L.nmax;
+    const size_t M2 = (size_t)M * M, base = (size_t)m * M2;
+    for (size_t x = blockIdx.x * (size_t)blockDim.x + threadIdx.x; x < M2;
+         x += (size_t)gridDim.x * blockDim.x) {
+        const size_t i = x / M, j = x - i * M;
+        E[base + x] = A[base + x] - A[base + j * M + i];
+    }
+}
+
+__global__ void k_diff2_padded(MolLayout L, const double *__restrict__ A,
+                               const double *__restrict__ B, double *out) {
+    __shared__ double red[256];
+    const int m = blockIdx.y, M = L.nmax;
+    const size_t M2 = (size_t)M * M, base = (size_t)m * M2;
+    double acc = 0.0;
+    for (size_t x = blockIdx.x * (size_t)blockDim.x + threadIdx.x; x < M2;
+         x += (size_t)gridDim.x * blockDim.x) {
+        const double d = A[base + x] - B[base + x];
+        acc += d * d;
+    }
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int o = blockDim.x / 2; o > 0; o >>= 1) {
+        if ((int)threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) atomicAdd(&out[m], red[0]);
+}
+
+// grid: (blocks, nmol, cnt)
+__global__ void k_dots_padded(MolLayout L, const double *__restrict__ En, DiisPtrs H, int cnt,
+                              double *out) {
+    __shared__ double red[256];
+    const int m = blockIdx.y, k = blockIdx.z, M = L.nmax;
+    const size_t M2 = (size_t)M * M, base = (size_t)m * M2;
+    const double *__restrict__ Hk = H.m[k];
+    double acc = 0.0;
+    for (size_t x = blockIdx.x * (size_t)blockDim.x + threadIdx.x; x < M2;
+         x += (size_t)gridDim.x * blockDim.x)
+        acc += En[base + x] * Hk[base + x];
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int o = blockDim.x / 2; o > 0; o >>= 1) {
+        if ((int)threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) atomicAdd(&out[(size_t)m * cnt + k], red[0]);
+}
+
+__global__ void k_lincomb_padded(MolLayout L, DiisPtrs H, int cnt, const double *__restrict__ coef,
+                                 double *out) {
+    const int m = blockIdx.y, M = L.nmax;
+    const size_t M2 = (size_t)M * M, base = (size_t)m * M2;
+    for (size_t x = blockIdx.x * (size_t)blockDim.x + threadIdx.x; x < M2;
+         x += (size_t)gridDim.x * blockDim.x) {
+        double v = 0.0;
+        for (int k = 0; k < cnt; ++k) v += coef[(size_t)m * cnt + k] * H.m[k][base + x];
+        out[base + x] = v;
+    }
+}
+
+__global__ void k_scale_cols_padded(MolLayout L, const double *__restrict__ U,
+                                    const double *__restrict__ w, double *out) {
+    const int m = blockIdx.y, M = L.nmax;
+    const size_t M2 = (size_t)M * M, base = (size_t)m * M2;
+    for (size_t x = blockIdx.x * (size_t)blockDim.x + threadIdx.x; x < M2;
+         x += (size_t)gridDim.x * blockDim.x)
+        out[base + x] = U[base + x] * w[(size_t)m * M + x / M];
+}
+
+static inline dim3 grid_mol(size_t per_mol, int nmol, int z = 1) {
+    size_t b = (per_mol + 255) / 256;
+    if (b > 64) b = 64;
+    if (b < 1) b = 1;
+    return dim3((unsigned)b, (unsigned)nmol, (unsigned)z);
+}
+
+hipError_t assemble_fock_packed(const MolLayout &L, const double *Jh, const double *Kh,
+                                const double *H, double *F, double *J, double *K, hipStream_t s) {
+    hipLaunchKernelGGL(k_assemble_packed, grid_mol((size_t)L.nmax * L.nmax, L.nmol), dim3(256), 0,
+                       s, L, Jh, Kh, H, F, J, K);
+    return hipGetLastError();
+}
+hipError_t dot3_packed(const MolLayout &L, const double *A, const double *B, const double *C,
+                       double w, double *E, hipStream_t s) {
+    hipLaunchKernelGGL(k_dot3_packed, grid_mol((size_t)L.nmax * L.nmax, L.nmol), dim3(256), 0, s,
+                       L, A, B, C, w, E);
+    return hipGetLastError();
+}
+hipError_t pad_blocks(const MolLayout &L, const double *packed, double *padded, double diag,
+                      hipStream_t s) {
+    hipLaunchKernelGGL(k_pad, grid_mol((size_t)L.nmax * L.nmax, L.nmol), dim3(256), 0, s, L,
+                       packed, padded, diag);
+    return hipGetLastError();
+}
+hipError_t unpad_blocks(const MolLayout &L, const double *padded, double *packed, hipStream_t s) {
+    hipLaunchKernelGGL(k_unpad, grid_mol((size_t)L.nmax * L.nmax, L.nmol), dim3(256), 0, s, L,
+                       padded, packed);
+    return hipGetLastError();
+}
+hipError_t pad_diag(const MolLayout &L, double *padded, double big, hipStream_t s) {
+    hipLaunchKernelGGL(k_pad_diag, grid_mol((size_t)L.nmax * L.nmax, L.nmol), dim3(256), 0, s, L,
+                       padded, big);
+    return hipGetLastError();
+}
+hipError_t mask_cols(const MolLayout &L, const int *nocc, double *C, hipStream_t s) {
+    hipLaunchKernelGGL(k_mask_cols, grid_mol((size_t)L.nmax * L.nmax, L.nmol), dim3(256), 0, s, L,
+                       nocc, C);
+    return hipGetLastError();
+}
+hipError_t antisym_padded(const MolLayout &L, const double *A, double *E, hipStream_t s) {
+    hipLaunchKernelGGL(k_antisym_padded, grid_mol((size_t)L.nmax * L.nmax, L.nmol), dim3(256), 0,
+                       s, L, A, E);
+    return hipGetLastError();
+}
+hipError_t diff2_padded(const MolLayout &L, const double *A, const double *B, double *out,
+                        hipStream_t s) {
+    hipLaunchKernelGGL(k_diff2_padded, grid_mol((size_t)L.nmax * L.nmax, L.nmol), dim3(256), 0, s,
+                       L, A, B, out);
+    return hipGetLastError();
+}
+hipError_t dots_padded(const MolLayout &L, const double *Enew, const DiisPtrs &hist, int cnt,
+                       double *out, hipStream_t s) {
+    hipLaunchKernelGGL(k_dots_padded, grid_mol((size_t)L.nmax * L.nmax, L.nmol, cnt), dim3(256),
+                       0, s, L, Enew, hist, cnt, out);
+    return hipGetLastError();
+}
+hipError_t lincomb_padded(const MolLayout &L, const DiisPtrs &hist, int cnt, const double *coef,
+                          double *out, hipStream_t s) {
+    hipLaunchKernelGGL(k_lincomb_padded, grid_mol((size_t)L.nmax * L.nmax, L.nmol), dim3(256), 0,
+                       s, L, hist, cnt, coef, out);
+    return hipGetLastError();
+}
+
+hipError_t scale_cols_padded(const MolLayout &L, const double *U, const double *w, double *out,
+                             hipStream_t s) {
+    hipLaunchKernelGGL(k_scale_cols_padded, grid_mol((size_t)L.nmax * L.nmax, L.nmol), dim3(256),
+                       0, s, L, U, w, out);
+    return hipGetLastError();
+}
+
 static inline dim3 grid_for(size_t n) {
     size_t b = (n + 255) / 256;
     if (b > 4096) b = 4096;

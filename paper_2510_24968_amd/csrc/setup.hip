@@ -128,6 +128,7 @@ __global__ void k_build_pairs(ShellsDev sh, PairTable t, const int *__restrict__
         t.sh2[pr] = s2;
         t.bf1[pr] = sh.bf0[s1];
         t.bf2[pr] = sh.bf0[s2];
+        t.mol[pr] = sh.mol[s1];
         t.nprim[pr] = np1 * np2;
     }
     const size_t n = t.n;
@@ -233,14 +234,17 @@ __device__ inline void r_table_rt(int L, const double *src, double X, double Y, 
     }
 }
 
-__global__ void k_one_electron(ShellsDev sh, const double *__restrict__ boys, int nbf,
+__global__ void k_one_electron(ShellsDev sh, const double *__restrict__ boys,
                                const int *__restrict__ bf_shell, const int *__restrict__ bf_comp,
                                double *S, double *T, double *V) {
+    // one molecule per grid z, element (mu, nu) of its packed block
+    const int m = blockIdx.z, nm = sh.mol_n[m];
     const int mu = blockIdx.y, nu = blockIdx.x * blockDim.x + threadIdx.x;
-    if (nu >= nbf) return;
-    const int s1 = bf_shell[mu], s2 = bf_shell[nu];
+    if (mu >= nm || nu >= nm) return;
+    const int g0 = sh.mol_bf0[m];
+    const int s1 = bf_shell[g0 + mu], s2 = bf_shell[g0 + nu];
     const int l1 = sh.l[s1], l2 = sh.l[s2];
-    const int c1 = bf_comp[mu], c2 = bf_comp[nu];
+    const int c1 = bf_comp[g0 + mu], c2 = bf_comp[g0 + nu];
     int i[3], j[3];
     for (int d = 0; d < 3; ++d) {
         i[d] = cart_exp(l1, c1, d);
@@ -273,7 +277,8 @@ __global__ void k_one_electron(ShellsDev sh, const double *__restrict__ boys, in
             tacc += cc * f3 * (tk[0] * e0[1] * e0[2] + e0[0] * tk[1] * e0[2] + e0[0] * e0[1] * tk[2]);
             const int L = l1 + l2;
             double vsum = 0.0;
-            for (int C = 0; C < sh.natom; ++C) {
+            const int a0 = sh.mol_atom0[m];
+            for (int C = a0; C < a0 + sh.mol_natom[m]; ++C) {
                 const double X = P[0] - sh.atom_xyz[3 * C], Y = P[1] - sh.atom_xyz[3 * C + 1],
                              Zc = P[2] - sh.atom_xyz[3 * C + 2];
                 double F[2 * LMAX + 1], src[2 * LMAX + 1], r[nherm(2 * LMAX)];
@@ -294,16 +299,17 @@ __global__ void k_one_electron(ShellsDev sh, const double *__restrict__ boys, in
             }
             vacc += cc * 2.0 * M_PI / p * vsum;
         }
-    S[(size_t)mu * nbf + nu] = sacc;
-    T[(size_t)mu * nbf + nu] = tacc;
-    V[(size_t)mu * nbf + nu] = vacc;
+    const size_t o = (size_t)sh.mol_off[m] + (size_t)mu * nm + nu;
+    S[o] = sacc;
+    T[o] = tacc;
+    V[o] = vacc;
 }
 
-hipError_t launch_one_electron_impl(const ShellsDev &sh, const double *boys, int nbf,
+hipError_t launch_one_electron_impl(const ShellsDev &sh, const double *boys, int nmax,
                                     const int *bf_shell, const int *bf_comp, double *S,
                                     double *T, double *V, hipStream_t s) {
-    dim3 g((nbf + 63) / 64, nbf), b(64);
-    hipLaunchKernelGGL(k_one_electron, g, b, 0, s, sh, boys, nbf, bf_shell, bf_comp, S, T, V);
+    dim3 g((nmax + 63) / 64, nmax, sh.nmol), b(64);
+    hipLaunchKernelGGL(k_one_electron, g, b, 0, s, sh, boys, bf_shell, bf_comp, S, T, V);
     return hipGetLastError();
 }
 

@@ -103,6 +103,11 @@ def lib():
         "fsim_scf_reset": [vp],
         "fsim_eri_quartets": [vp, i64, vp, vp, vp, ctypes.c_int, vp],
         "fsim_set_profiling": [vp, i32],
+        "fsim_batch_create": [vp, i32, ctypes.POINTER(_Options), ctypes.POINTER(vp)],
+        "fsim_batch_layout": [vp, ctypes.POINTER(i32), vp, vp, vp, ctypes.POINTER(i64)],
+        "fsim_batch_energies": [vp, vp],
+        "fsim_batch_scf_info": [vp, vp],
+        "fsim_set_graph": [vp, i32],
         "fsim_set_tuning": [vp, vp, i32],
         "fsim_get_tuning": [vp, vp, i32, ctypes.POINTER(i32)],
         "fsim_autotune": [vp, vp, ctypes.c_int, vp],
@@ -171,6 +176,7 @@ class Context:
         self.nelec = int(basis["nelec"])
         self.tau, self.tau_fp32 = float(tau), float(tau_fp32)
         self.shell_l = np.asarray(basis["shell_l"], dtype=np.int32)
+        self.packed = self.nbf * self.nbf
         self.screen_stats = None
 
     def close(self):
@@ -204,7 +210,7 @@ class Context:
         return Q, self.screen_stats
 
     def fock_build(self, D, precision="fp64", want_jk=False, energy=True, F=None):
-        assert D.dtype == torch.float64 and D.is_contiguous() and D.shape == (self.nbf, self.nbf)
+        assert D.dtype == torch.float64 and D.is_contiguous() and D.numel() == self.packed
         F = self._mat() if F is None else F
         J = self._mat() if want_jk else None
         K = self._mat() if want_jk else None
@@ -321,4 +327,109 @@ class Context:
             r = self.fock_build(Din, "fp64")
             res["E_total_mixed"] = info["E_total"]
             res["E_total"] = r["E_elec"] + self.enuc
+        return res
+
+
+class Batch(Context):
+    """Many molecules in one context: every matrix is a packed 1-D tensor
+    holding molecule m's N_m x N_m block at offsets[m]."""
+
+    def __init__(self, bases, tau=0.0, tau_fp32=0.0, diis_m=8, conv_rms_dD=1e-8, conv_dE=1e-10,
+                 max_iter=100, device="cuda"):
+        L = lib()
+        if not torch.cuda.is_available():
+            raise FsimError("no GPU: libfsim runs on an MI355X only")
+        self.device = torch.device(device)
+        structs, keeps = [], []
+        for b in bases:
+            st, keep = basis_struct(b)
+            structs.append(st)
+            keeps.append(keep)
+        arr = (_Basis * len(structs))(*structs)
+        self.opt = _Options(float(tau), float(tau_fp32), int(diis_m), float(conv_rms_dD),
+                            float(conv_dE), int(max_iter))
+        h = ctypes.c_void_p()
+        with torch.cuda.device(self.device):
+            _check(L.fsim_batch_create(arr, len(structs), ctypes.byref(self.opt), ctypes.byref(h)))
+        self.h = h
+        n, ns = ctypes.c_int32(), ctypes.c_int32()
+        _check(L.fsim_nbf(self.h, ctypes.byref(n), ctypes.byref(ns)))
+        self.nbf, self.nshell = n.value, ns.value
+        self.nmol = len(bases)
+        nm = ctypes.c_int32()
+        self.nbf_mol = np.zeros(self.nmol, dtype=np.int32)
+        self.offsets = np.zeros(self.nmol, dtype=np.int64)
+        self.enuc_mol = np.zeros(self.nmol)
+        packed = ctypes.c_int64()
+        _check(L.fsim_batch_layout(self.h, ctypes.byref(nm), self.nbf_mol.ctypes.data,
+                                   self.offsets.ctypes.data, self.enuc_mol.ctypes.data,
+                                   ctypes.byref(packed)))
+        self.packed = packed.value
+        self.enuc = float(self.enuc_mol.sum())
+        self.nelec = int(sum(int(b["nelec"]) for b in bases))
+        self.tau, self.tau_fp32 = float(tau), float(tau_fp32)
+        self.shell_l = np.concatenate([np.asarray(b["shell_l"], dtype=np.int32) for b in bases])
+        self.screen_stats = None
+
+    def _mat(self):
+        return torch.empty(self.packed, dtype=torch.float64, device=self.device)
+
+    def unpack(self, packed):
+        return [packed[o:o + n * n].view(n, n) for o, n in zip(self.offsets, self.nbf_mol)]
+
+    def pack(self, blocks):
+        return torch.cat([b.reshape(-1) for b in blocks]).contiguous()
+
+    def schwarz_screen(self, tau=None, tau_fp32=None, want_q=False):
+        return super().schwarz_screen(tau, tau_fp32, want_q=False)
+
+    def energies(self):
+        E = np.zeros(self.nmol)
+        _check(lib().fsim_batch_energies(self.h, E.ctypes.data))
+        return E
+
+    def scf_info(self):
+        arr = (_ScfInfo * self.nmol)()
+        _check(lib().fsim_batch_scf_info(self.h, arr))
+        return [_struct_dict(arr[k]) for k in range(self.nmol)]
+
+    def set_graph(self, enable=True):
+        _check(lib().fsim_set_graph(self.h, 1 if enable else 0))
+
+    def one_electron(self):
+        S, H, X = self._mat(), self._mat(), self._mat()
+        _check(lib().fsim_one_electron(self.h, _ptr(S), _ptr(H), _ptr(X), _stream()))
+        return S, H, X
+
+    def scf(self, precision="fp64", max_iter=100, D0=None, verbose=False, refine=True):
+        """All molecules at once; each molecule's energy and the iteration at
+        which it first met the convergence test are returned."""
+        if self.screen_stats is None:
+            self.schwarz_screen(want_q=False)
+        self.scf_reset()
+        D = self.core_guess() if D0 is None else D0.clone()
+        first_conv = np.full(self.nmol, -1)
+        info = None
+        per = None
+        Din = None
+        for _ in range(max_iter):
+            Din = D.clone() if precision == "mixed" else None
+            info = self.scf_step(D, precision)
+            per = self.scf_info()
+            for m, r in enumerate(per):
+                if r["converged"] and first_conv[m] < 0:
+                    first_conv[m] = r["iter"]
+            if verbose:
+                print(f"fsim batch scf {info['iter']:3d} sumE={info['E_total']:.10f} "
+                      f"max rmsD={info['rms_dD']:.2e} converged {int((first_conv >= 0).sum())}"
+                      f"/{self.nmol}", flush=True)
+            if info["converged"]:
+                break
+        E = np.array([r["E_total"] for r in per])
+        res = {"E_total": E, "iterations": info["iter"], "converged": bool(info["converged"]),
+               "first_converged": first_conv, "D": D, "per_molecule": per}
+        if precision == "mixed" and refine:
+            self.fock_build(Din, "fp64")
+            res["E_total_mixed"] = E
+            res["E_total"] = self.energies() + self.enuc_mol
         return res

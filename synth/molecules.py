@@ -162,6 +162,9 @@ WORKLOADS = {
                     conv_rms_dD=1e-8, conv_dE=1e-10),
     "water64": dict(kind="water", nmol=64, seed=3, tau=1e-11, tau_fp32=1e-5,
                     conv_rms_dD=1e-8, conv_dE=1e-10),
+    # 1024 random-walk C/H molecules of 2-24 atoms, run as one batch
+    "ch1024": dict(kind="batch", count=1024, seed0=4_000_000, tau=1e-11, tau_fp32=1e-5,
+                   conv_rms_dD=1e-8, conv_dE=1e-10),
 }
 
 
@@ -173,6 +176,8 @@ def workload(name):
         b = h_chain(w.pop("natom"), w.pop("spacing"))
     elif kind == "water":
         b = water_cluster(w.pop("nmol"), w.pop("seed"))
+    elif kind == "batch":
+        b = batch_molecules(w.pop("count"), w.pop("seed0"))
     else:
         raise KeyError(kind)
     return b, w

@@ -263,6 +263,51 @@ fsim_status fsim_batch_scf_info(const fsim_ctx *ctx, fsim_scf_info *info);
  * direct launches. */
 fsim_status fsim_set_graph(fsim_ctx *ctx, int32_t enable);
 
+/* McWeeny purification of a trial density of a one-molecule context: with
+ * P = D/2, P <- 3 PSP - 2 PSPSP, at most iters times or until
+ * ||PSP - P||_F / ||P||_F < 1e-12 (idempotency of the closed-shell density,
+ * D = 2 C_occ C_occ^T, Sec. 2.2 Eq. density).  D: device N x N, overwritten.
+ * err_in / err_out (host, may be NULL): the measure before and after. */
+fsim_status fsim_purify(fsim_ctx *ctx, double *D, int32_t iters, double *err_in, double *err_out,
+                        void *stream);
+
+/* ---- learned initial guess: BF16 matrix-core kernels -------------------- */
+/* BF16 values are raw uint16_t bit patterns (round-to-nearest-even from
+ * FP32).  All pointers are device memory; calls are asynchronous on stream
+ * and return FSIM_EINVAL for bad sizes / NULL pointers, FSIM_EHIP on a
+ * launch failure. */
+
+/* C[M x N] = op(A)[M x K] op(B)[K x N] with FP32 accumulation on
+ * v_mfma_f32_16x16x16bf16_1k.  A, B: BF16 row-major with leading dimensions
+ * lda, ldb; ta / tb = 1 reads them transposed.  Epilogue: C = act(acc + bias)
+ * with act = ReLU when relu = 1 (bias: FP32 [N] or NULL); the result goes to
+ * C (FP32, leading dimension ldc) and/or Cb (BF16, same layout).  ksplit > 1
+ * splits K over that many blocks and adds the partial sums atomically into C
+ * (the caller zeroes C first; no bias, ReLU or Cb then). */
+fsim_status fsim_gemm_bf16(int32_t M, int32_t N, int32_t K, const uint16_t *A, int32_t lda,
+                           int32_t ta, const uint16_t *B, int32_t ldb, int32_t tb, float *C,
+                           int32_t ldc, uint16_t *Cb, const float *bias, int32_t relu,
+                           int32_t ksplit, void *stream);
+
+/* y = bf16(x) for n values. */
+fsim_status fsim_f32_to_bf16(int64_t n, const float *x, uint16_t *y, void *stream);
+
+/* dH <- dH * [H > 0] (FP32) and, if dHb is not NULL, its BF16 copy. */
+fsim_status fsim_relu_backward(int64_t n, const float *H, float *dH, uint16_t *dHb, void *stream);
+
+/* db[j] = sum_i dY[i*m + j] for an n x m FP32 matrix. */
+fsim_status fsim_bias_grad(int32_t n, int32_t m, const float *dY, float *db, void *stream);
+
+/* Masked mean-square error: *loss += sum mask (Y - T)^2 * inv_count and
+ * dY = 2 mask (Y - T) inv_count (n values; loss is a device scalar). */
+fsim_status fsim_mse(int64_t n, const float *Y, const float *T, const float *mask, float inv_count,
+                     float *dY, float *loss, void *stream);
+
+/* One Adam step (bias-corrected, step >= 1) on FP32 master weights w with
+ * gradient g and moments m1, m2; wb (BF16 copy of w) is refreshed if given. */
+fsim_status fsim_adam(int64_t n, float *w, const float *g, float *m1, float *m2, float lr,
+                      float b1, float b2, float eps, int32_t step, uint16_t *wb, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

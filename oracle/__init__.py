@@ -26,6 +26,10 @@ besides itself; see tests/test_oracle_pins.py):
                   convergence, two-centre minimal-basis closed form,
                   invariance under rigid motions and atom permutations,
                   variational rise under idempotent perturbations.
+  mcweeny         pinned: fixed points are the SCF densities; the
+                  idempotency error falls quadratically on a perturbed one.
+  mlp (module)    pinned: finite differences of the loss; the BF16 rounding
+                  against torch's own float -> bfloat16 conversion.
 """
 
 import ctypes
@@ -269,6 +273,22 @@ def density_from_fock(F, X, nocc):
     C = X @ Cp
     Co = C[:, :nocc]
     return 2.0 * Co @ Co.T, eps, C
+
+
+def mcweeny(D, S, iters):
+    """McWeeny purification of a closed-shell density (an extension: not in
+    the paper): with P = D / 2, P <- 3 P S P - 2 P S P S P, repeated.
+    Returns the purified D and ||PSP - P||_F / ||P||_F before and after."""
+    P = 0.5 * np.asarray(D, dtype=np.float64)
+
+    def err(P):
+        return np.linalg.norm(P @ S @ P - P) / max(np.linalg.norm(P), 1e-300)
+
+    e0 = err(P)
+    for _ in range(iters):
+        PS = P @ S
+        P = 3.0 * PS @ P - 2.0 * PS @ PS @ P
+    return 2.0 * P, e0, err(P)
 
 
 def diis_extrapolate(Fs, es):

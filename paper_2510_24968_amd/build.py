@@ -23,7 +23,8 @@ _PC = ("ss", "ps", "pp", "ds", "dp", "dd")
 ERI_SOURCES = [f"eri_{_PC[b]}{_PC[k]}_{p}.hip" for b in range(6) for k in range(b + 1)
                for p in ("f64", "f32")]
 # slowest (highest angular momentum) first so the pool stays busy
-SOURCES = ERI_SOURCES[::-1] + ["eri_dispatch.hip", "setup.hip", "linalg.hip", "api.cpp"]
+SOURCES = ERI_SOURCES[::-1] + ["eri_dispatch.hip", "setup.hip", "linalg.hip", "mlp.hip",
+                                "api.cpp"]
 
 FLAGS = [
     f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC",

@@ -1545,3 +1545,55 @@ extern "C" fsim_status fsim_set_graph(fsim_ctx *c, int32_t enable) {
     c->graph_enabled = enable != 0;
     return FSIM_OK;
 }
+
+// ---------------------------------------------------------------------------
+// McWeeny purification (one molecule)
+// ---------------------------------------------------------------------------
+extern "C" fsim_status fsim_purify(fsim_ctx *c, double *D, int32_t iters, double *err_in,
+                                   double *err_out, void *stream) {
+    if (!c || !D) return fail(FSIM_EINVAL, "NULL argument");
+    if (c->nmol != 1) return fail(FSIM_EINVAL, "purification is for one-molecule contexts");
+    if (iters < 0) return fail(FSIM_EINVAL, "iters must be >= 0");
+    hipStream_t s = (hipStream_t)stream;
+    const int N = c->nbf;
+    const size_t N2 = (size_t)N * N;
+    BLASCHK(rocblas_set_stream(c->blas, s));
+    // work on P = D / 2 in Dn
+    auto measure = [&](double *P, double &err) -> fsim_status {
+        STCHK(gemm(c->blas, false, false, N, N, N, 1.0, c->S, N, P, N, 0.0, c->T1, N));   // S P
+        STCHK(gemm(c->blas, false, false, N, N, N, 1.0, P, N, c->T1, N, 0.0, c->T2, N));  // P S P
+        HIPCHK(fill(c->scal + 3, 2, 0.0, s));
+        HIPCHK(diff2(N2, c->T2, P, c->scal + 3, s));
+        HIPCHK(dot3(N2, P, P, nullptr, 1.0, c->scal + 4, s));
+        double h[2];
+        HIPCHK(hipMemcpyAsync(h, c->scal + 3, sizeof(double) * 2, hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        err = std::sqrt(h[0]) / std::max(std::sqrt(h[1]), 1e-300);
+        return FSIM_OK;
+    };
+    HIPCHK(hipMemcpyAsync(c->Dn, D, sizeof(double) * N2, hipMemcpyDeviceToDevice, s));
+    {
+        const double half = 0.5;
+        BLASCHK(rocblas_dscal(c->blas, (int)N2, &half, c->Dn, 1));
+    }
+    double err = 0.0;
+    STCHK(measure(c->Dn, err));
+    if (err_in) *err_in = err;
+    for (int it = 0; it < iters && err >= 1e-12 && std::isfinite(err); ++it) {
+        // T2 = PSP, T1 = SP from measure; Jh = PSP S P; P <- 3 PSP - 2 PSPSP
+        STCHK(gemm(c->blas, false, false, N, N, N, 1.0, c->T2, N, c->T1, N, 0.0, c->Jh, N));
+        HIPCHK(hipMemcpyAsync(c->Dn, c->T2, sizeof(double) * N2, hipMemcpyDeviceToDevice, s));
+        const double three = 3.0, mtwo = -2.0;
+        BLASCHK(rocblas_dscal(c->blas, (int)N2, &three, c->Dn, 1));
+        BLASCHK(rocblas_daxpy(c->blas, (int)N2, &mtwo, c->Jh, 1, c->Dn, 1));
+        STCHK(measure(c->Dn, err));
+    }
+    if (err_out) *err_out = err;
+    HIPCHK(hipMemcpyAsync(D, c->Dn, sizeof(double) * N2, hipMemcpyDeviceToDevice, s));
+    {
+        const double two = 2.0;
+        BLASCHK(rocblas_dscal(c->blas, (int)N2, &two, D, 1));
+    }
+    HIPCHK(hipStreamSynchronize(s));
+    return FSIM_OK;
+}

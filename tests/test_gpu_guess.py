@@ -1,0 +1,234 @@
+"""Learned initial guess on the GPU, through the C ABI: the BF16 matrix-core
+GEMM against a CPU FP32 product of the same BF16 inputs, the training
+kernels against numpy, forward/backward against the FP64 network oracle,
+McWeeny purification against the oracle's, and a small train -> guess ->
+SCF run.
+
+Tolerances: the GEMM's FP32 accumulation differs from the CPU's only in
+summation order, so |C - C_ref| <= K 2^-23 (|A| |B|) elementwise; BF16
+outputs are bit-exact (both sides round the same FP32 value to nearest
+even).  Gradients against the oracle that rounds at the same points as the
+GPU: relative norm error 1e-3 (FP32 accumulation order can flip single BF16
+roundings, each worth 2^-8 relative)."""
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from oracle import mlp as omlp
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+def _g():
+    from paper_2510_24968_amd import guess
+    return guess
+
+
+def _bf16_pair(shape, gen, scale=1.0):
+    """(int16 bits on the GPU, FP64 values on the CPU) of random BF16 numbers."""
+    x = (torch.randn(shape, generator=gen) * scale).to(torch.bfloat16)
+    return x.view(torch.int16).cuda(), x.double().numpy()
+
+
+@pytest.mark.parametrize("M,N,K", [(70, 37, 40), (128, 256, 64), (5, 3, 17), (256, 36, 1000)])
+@pytest.mark.parametrize("ta,tb", [(0, 0), (1, 0), (0, 1), (1, 1)])
+def test_gemm_bf16_matches_cpu(M, N, K, ta, tb):
+    g = _g()
+    print(f"[gpu] gemm {M}x{N}x{K} ta={ta} tb={tb}", flush=True)
+    gen = torch.Generator().manual_seed(M * 1000 + N + K + 7 * ta + 13 * tb)
+    Ad, A = _bf16_pair((K, M) if ta else (M, K), gen)
+    Bd, B = _bf16_pair((N, K) if tb else (K, N), gen)
+    bias = torch.randn(N, generator=gen).float()
+    opA = A.T if ta else A
+    opB = B.T if tb else B
+    ref = opA @ opB
+    bound = K * 2.0 ** -23 * (np.abs(opA) @ np.abs(opB)) + 1e-30
+    lda = M if ta else K
+    ldb = K if tb else N
+    # plain product
+    C = torch.empty(M, N, dtype=torch.float32, device="cuda")
+    g.GuessNet.gemm(M, N, K, Ad, lda, ta, Bd, ldb, tb, C=C)
+    assert np.all(np.abs(C.cpu().double().numpy() - ref) <= bound)
+    # bias + ReLU epilogue with the BF16 copy
+    C2 = torch.empty(M, N, dtype=torch.float32, device="cuda")
+    Cb = torch.empty(M, N, dtype=torch.int16, device="cuda")
+    g.GuessNet.gemm(M, N, K, Ad, lda, ta, Bd, ldb, tb, C=C2, Cb=Cb, bias=bias.cuda(), relu=True)
+    ref2 = np.maximum(ref + bias.double().numpy()[None, :], 0.0)
+    c2 = C2.cpu()
+    assert np.all(np.abs(c2.double().numpy() - ref2) <= bound + 1e-6 * np.abs(ref2))
+    assert torch.equal(Cb.cpu(), c2.to(torch.bfloat16).view(torch.int16))
+    # split-K into a zeroed accumulator
+    for ks in (2, 7):
+        C3 = torch.zeros(M, N, dtype=torch.float32, device="cuda")
+        g.GuessNet.gemm(M, N, K, Ad, lda, ta, Bd, ldb, tb, C=C3, ksplit=ks)
+        assert np.all(np.abs(C3.cpu().double().numpy() - ref) <= bound)
+
+
+def test_gemm_rejects_bad_arguments():
+    g = _g()
+    L = g._lib()
+    x = torch.zeros(16, dtype=torch.int16, device="cuda")
+    c = torch.zeros(16, dtype=torch.float32, device="cuda")
+    s = g._stream()
+    assert L.fsim_gemm_bf16(0, 4, 4, g._p(x), 4, 0, g._p(x), 4, 0, g._p(c), 4, None, None, 0, 1, s) != 0
+    # split-K cannot take an epilogue
+    assert L.fsim_gemm_bf16(4, 4, 4, g._p(x), 4, 0, g._p(x), 4, 0, g._p(c), 4, None, None, 1, 2, s) != 0
+
+
+def test_f32_to_bf16_matches_torch_rounding():
+    g = _g()
+    rng = np.random.default_rng(1)
+    x = np.concatenate([rng.standard_normal(100000) * 10.0 ** rng.integers(-30, 30, 100000),
+                        [0.0, -0.0, 1.0 + 2.0 ** -8, 1.0 + 3 * 2.0 ** -8, 3.0e38, 1e-40, np.inf,
+                         -np.inf]]).astype(np.float32)
+    xt = torch.from_numpy(x)
+    got = g.GuessNet.to_bf16(xt.cuda()).cpu()
+    assert torch.equal(got, xt.to(torch.bfloat16).view(torch.int16))
+
+
+def test_training_kernels_against_numpy():
+    g = _g()
+    L = g._lib()
+    s = g._stream()
+    rng = np.random.default_rng(2)
+    n, m = 3001, 37
+    H = rng.standard_normal((n, m)).astype(np.float32)
+    dH = rng.standard_normal((n, m)).astype(np.float32)
+    Ht, dHt = torch.from_numpy(H).cuda(), torch.from_numpy(dH).cuda()
+    dHb = torch.empty(n, m, dtype=torch.int16, device="cuda")
+    assert L.fsim_relu_backward(n * m, g._p(Ht), g._p(dHt), g._p(dHb), s) == 0
+    ref = np.where(H > 0, dH, 0.0).astype(np.float32)
+    assert np.array_equal(dHt.cpu().numpy(), ref)
+    assert torch.equal(dHb.cpu(), torch.from_numpy(ref).to(torch.bfloat16).view(torch.int16))
+    db = torch.empty(m, dtype=torch.float32, device="cuda")
+    assert L.fsim_bias_grad(n, m, g._p(Ht), g._p(db), s) == 0
+    assert np.allclose(db.cpu().numpy(), H.astype(np.float64).sum(0), rtol=0,
+                       atol=n * 2.0 ** -23 * np.abs(H).sum(0).max())
+    T = rng.standard_normal((n, m)).astype(np.float32)
+    mask = (rng.random((n, m)) < 0.6).astype(np.float32)
+    loss = torch.zeros(1, dtype=torch.float32, device="cuda")
+    dY = torch.empty(n, m, dtype=torch.float32, device="cuda")
+    Tt, Mt = torch.from_numpy(T).cuda(), torch.from_numpy(mask).cuda()
+    inv = 1.0 / mask.sum()
+    assert L.fsim_mse(n * m, g._p(Ht), g._p(Tt), g._p(Mt), inv, g._p(dY), g._p(loss), s) == 0
+    d = (H.astype(np.float64) - T) * mask
+    assert abs(loss.item() - (d * d).sum() * inv) < 1e-5 * (d * d).sum() * inv
+    assert np.allclose(dY.cpu().numpy(), 2 * d * inv, rtol=1e-6, atol=1e-12)
+    # Adam, three steps, against the textbook update in FP64
+    w = rng.standard_normal(1000).astype(np.float32)
+    wt = torch.from_numpy(w.copy()).cuda()
+    m1 = torch.zeros(1000, device="cuda")
+    m2 = torch.zeros(1000, device="cuda")
+    wb = torch.empty(1000, dtype=torch.int16, device="cuda")
+    wr, a1, a2 = w.astype(np.float64), np.zeros(1000), np.zeros(1000)
+    for step in range(1, 4):
+        gr = rng.standard_normal(1000).astype(np.float32)
+        assert L.fsim_adam(1000, g._p(wt), g._p(torch.from_numpy(gr).cuda()), g._p(m1), g._p(m2),
+                           1e-2, 0.9, 0.999, 1e-8, step, g._p(wb), s) == 0
+        a1 = 0.9 * a1 + 0.1 * gr
+        a2 = 0.999 * a2 + 0.001 * gr.astype(np.float64) ** 2
+        wr = wr - 1e-2 * (a1 / (1 - 0.9 ** step)) / (np.sqrt(a2 / (1 - 0.999 ** step)) + 1e-8)
+    assert np.allclose(wt.cpu().numpy(), wr, rtol=0, atol=1e-5)
+    assert torch.equal(wb.cpu(), wt.cpu().to(torch.bfloat16).view(torch.int16))
+
+
+def _net_and_batch(n=700, seed=3):
+    g = _g()
+    net = g.GuessNet(seed=seed)
+    rng = np.random.default_rng(seed)
+    X = rng.random((n, g.NIN)).astype(np.float32)
+    T = (rng.standard_normal((n, g.NOUT)) * 0.3).astype(np.float32)
+    M = (rng.random((n, g.NOUT)) < 0.5).astype(np.float32)
+    return net, X, T, M
+
+
+def test_forward_backward_against_oracle():
+    g = _g()
+    net, X, T, M = _net_and_batch()
+    W = [w.cpu().double().numpy() for w in net.W]
+    b = [v.cpu().double().numpy() for v in net.b]
+    Xb = net.to_bf16(torch.from_numpy(X).cuda())
+    loss, dW, db = net.gradients(Xb, torch.from_numpy(T).cuda(), torch.from_numpy(M).cuda())
+    Y = net.forward(Xb)[0].cpu().double().numpy()
+    # the oracle rounding at the same points
+    l16, gW16, gb16 = omlp.loss_and_grads(X, T, M, W, b, bf16=True)
+    y16 = omlp.forward(X, W, b, bf16=True)[2]
+    rel = lambda a, r: np.linalg.norm(a - r) / np.linalg.norm(r)
+    assert rel(Y, y16) < 1e-3
+    assert abs(loss.item() - l16) < 1e-3 * l16
+    for k in range(3):
+        e1, e2 = rel(dW[k].cpu().double().numpy(), gW16[k]), rel(db[k].cpu().double().numpy(), gb16[k])
+        print(f"layer {k}: dW rel {e1:.2e} db rel {e2:.2e}")
+        assert e1 < 1e-3 and e2 < 1e-3
+    # and against exact FP64 arithmetic: BF16 costs well under a percent
+    l64, gW64, _ = omlp.loss_and_grads(X, T, M, W, b)
+    assert abs(loss.item() - l64) < 2e-2 * l64
+    for k in range(3):
+        a = dW[k].cpu().double().numpy().ravel()
+        r = gW64[k].ravel()
+        assert a @ r / (np.linalg.norm(a) * np.linalg.norm(r)) > 0.999
+
+
+def test_training_reduces_loss():
+    g = _g()
+    net, X, T, M = _net_and_batch(n=4096, seed=4)
+    # a learnable target: a fixed smooth function of the features
+    T = np.tanh(X @ np.random.default_rng(5).standard_normal((g.NIN, g.NOUT)) * 0.2).astype(np.float32)
+    hist = net.train(X, T, M, epochs=30, batch=1024, lr=3e-3)
+    print("loss", hist[0], "->", hist[-1])
+    assert hist[-1] < 0.1 * hist[0]
+
+
+def test_purify_against_oracle():
+    g = _g()
+    from paper_2510_24968_amd import fsim
+    b = synth.water_cluster(2, 21)
+    ctx = fsim.Context(b)
+    r = ctx.scf()
+    S = ctx.one_electron()[0].cpu().numpy()
+    D = r["D"].cpu().numpy()
+    rng = np.random.default_rng(7)
+    E = rng.standard_normal(D.shape)
+    Dp = D + 3e-3 * (E + E.T)
+    Dt = torch.tensor(Dp, dtype=torch.float64, device="cuda")
+    e0, e1 = g.purify(ctx, Dt, 8)
+    Dref, r0, r1 = oracle.mcweeny(Dp, S, 8)
+    print("idempotency", e0, "->", e1, "oracle", r0, "->", r1)
+    assert abs(e0 - r0) < 1e-10 * max(r0, 1.0)
+    assert e1 < 1e-10 and r1 < 1e-10
+    assert np.abs(Dt.cpu().numpy() - Dref).max() < 1e-9
+    # a converged density is (nearly) a fixed point
+    Dc = r["D"].clone()
+    f0, f1 = g.purify(ctx, Dc, 2)
+    assert f0 < 1e-6 and f1 < 1e-12
+    assert (Dc - r["D"]).abs().max().item() < 1e-6
+    ctx.close()
+
+
+def test_learned_guess_small_end_to_end():
+    """Train on a few small molecules, guess a held-out water trimer, and
+    converge the SCF from it to the energy reached from the core guess."""
+    g = _g()
+    from paper_2510_24968_amd import fsim
+    mols = g.training_molecules(6, 10, seed0=7_000_000)
+    dens, idx = g.converged_densities(mols, chunk=16, log=print)
+    assert len(idx) >= 12
+    X, T, M = g.dataset([mols[i] for i in idx], dens)
+    net = g.GuessNet(seed=1)
+    hist = net.train(X, T, M, epochs=40, batch=2048, lr=2e-3)
+    print("loss", hist[0], "->", hist[-1])
+    assert hist[-1] < 0.2 * hist[0]
+    b = synth.water_cluster(3, 7_500_000)
+    ctx = fsim.Context(b, conv_rms_dD=1e-8, conv_dE=1e-10)
+    D0, info = g.learned_guess(net, ctx, b)
+    print("guess", info)
+    assert not info["fallback"]
+    r_core = ctx.scf()
+    r_learn = ctx.scf(D0=D0)
+    print("iterations core", r_core["iterations"], "learned", r_learn["iterations"])
+    assert r_core["converged"] and r_learn["converged"]
+    assert abs(r_core["E_total"] - r_learn["E_total"]) < 1e-7
+    ctx.close()

@@ -1,0 +1,239 @@
+"""Host-side parts of the learned initial guess: Cartesian shell rotations
+(pinned against the oracle's overlap integrals of a rotated molecule), the
+symmetry projectors, covariance of the assembled density, and the FP64
+network oracle (pinned by finite differences)."""
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from helpers import random_rotation, transformed
+from oracle import mlp as omlp
+from paper_2510_24968_amd import guess
+
+
+def _block_rotation(basis, Q):
+    sl = np.asarray(basis["shell_l"])
+    N = synth.nbf_of(basis)
+    M = np.zeros((N, N))
+    o = 0
+    for l in sl:
+        n = guess.NCART[l]
+        M[o:o + n, o:o + n] = guess.cart_rotation(l, Q)
+        o += n
+    return M
+
+
+def test_cart_rotation_of_p_shell_is_the_rotation():
+    Q = random_rotation(np.random.default_rng(1))
+    assert np.allclose(guess.cart_rotation(1, Q), Q, atol=1e-13)
+    assert np.allclose(guess.cart_rotation(0, Q), [[1.0]])
+    assert np.allclose(guess.cart_rotation(2, np.eye(3)), np.eye(6), atol=1e-13)
+
+
+@pytest.mark.parametrize("improper", [False, True])
+def test_cart_rotation_matches_oracle_overlap(improper):
+    """S of the rotated molecule = M S M^T, M block-diagonal of the shells'
+    Cartesian transformations (s, p and d shells)."""
+    b = synth.water_cluster(2, 7)
+    Q = random_rotation(np.random.default_rng(3))
+    if improper:
+        Q = Q @ np.diag([1.0, 1.0, -1.0])
+    S = oracle.Basis(b).one_electron()[0]
+    S2 = oracle.Basis(transformed(b, R=Q)).one_electron()[0]
+    M = _block_rotation(b, Q)
+    assert np.abs(M @ S @ M.T - S2).max() < 1e-12
+
+
+def test_cart_rotation_is_a_representation():
+    rng = np.random.default_rng(5)
+    Q1, Q2 = random_rotation(rng), random_rotation(rng)
+    for l in range(3):
+        T12 = guess.cart_rotation(l, Q1 @ Q2)
+        assert np.allclose(guess.cart_rotation(l, Q1) @ guess.cart_rotation(l, Q2), T12, atol=1e-12) or \
+            np.allclose(guess.cart_rotation(l, Q2) @ guess.cart_rotation(l, Q1), T12, atol=1e-12)
+
+
+def test_bond_frames_are_rotations_along_the_bond():
+    d = np.random.default_rng(2).standard_normal((50, 3))
+    R = guess.bond_frames(d)
+    assert np.allclose(R @ np.swapaxes(R, 1, 2), np.eye(3), atol=1e-13)
+    assert np.allclose(np.linalg.det(R), 1.0)
+    assert np.allclose(R[:, 2], d / np.linalg.norm(d, axis=1, keepdims=True))
+
+
+@pytest.mark.parametrize("which", ["bond", "site"])
+def test_projectors_idempotent_and_invariant(which):
+    PR = guess.PROJ_BOND if which == "bond" else guess.PROJ_SITE
+    rng = np.random.default_rng(4)
+    if which == "bond":
+        a = rng.uniform(0, 2 * np.pi)
+        Gs = [np.array([[np.cos(a), -np.sin(a), 0], [np.sin(a), np.cos(a), 0], [0, 0, 1]]),
+              np.diag([1.0, -1.0, 1.0])]
+    else:
+        Gs = [random_rotation(rng), -np.eye(3)]
+    for (la, lb), P in PR.items():
+        assert np.allclose(P @ P, P, atol=1e-12)
+        na, nb = guess.NCART[la], guess.NCART[lb]
+        X = np.zeros((6, 6))
+        X[:na, :nb] = rng.standard_normal((na, nb))
+        Y = (P @ X.ravel()).reshape(6, 6)[:na, :nb]
+        for G in Gs:       # invariant under continuous rotations too, not only the averaged set
+            Ta, Tb = guess.cart_rotation(la, G), guess.cart_rotation(lb, G)
+            assert np.allclose(Ta.T @ Y @ Tb, Y, atol=1e-12)
+
+
+def test_site_projector_known_forms():
+    P = guess.PROJ_SITE
+    rng = np.random.default_rng(6)
+    X = rng.standard_normal(36)
+    assert np.allclose(P[(0, 1)] @ X, 0.0, atol=1e-13)           # odd parity
+    assert np.allclose(P[(1, 2)] @ X, 0.0, atol=1e-13)
+    pp = (P[(1, 1)] @ X).reshape(6, 6)[:3, :3]
+    assert np.allclose(pp, np.trace(X.reshape(6, 6)[:3, :3]) / 3 * np.eye(3), atol=1e-12)
+    assert np.linalg.matrix_rank(P[(2, 2)], tol=1e-9) == 2     # the s-like and l = 2 invariants
+    assert np.linalg.matrix_rank(P[(1, 1)], tol=1e-9) == 1
+    assert np.linalg.matrix_rank(P[(0, 2)], tol=1e-9) == 1
+
+
+def test_bond_projector_ranks():
+    """C_inf_v invariants: sigma-only couplings for s, |m| matching for p/d."""
+    P = guess.PROJ_BOND
+    rank = {k: np.linalg.matrix_rank(v, tol=1e-9) for k, v in P.items()}
+    assert rank[(0, 0)] == 1 and rank[(0, 1)] == 1 and rank[(1, 1)] == 2
+    # d Cartesian: 6 functions = s-like + (m = 0, +-1, +-2); the m = 0 part counts twice
+    assert rank[(0, 2)] == 2 and rank[(1, 2)] == 3 and rank[(2, 2)] == 6
+
+
+def _fake_prediction(feats):
+    W = np.random.default_rng(9).standard_normal((guess.NIN, guess.NOUT)) * 0.3
+    return np.tanh(feats.astype(np.float64) @ W)
+
+
+@pytest.mark.parametrize("improper", [False, True])
+def test_assembled_density_is_covariant(improper):
+    b = synth.water_cluster(3, 11)
+    Q = random_rotation(np.random.default_rng(8))
+    if improper:
+        Q = -Q
+    b2 = transformed(b, R=Q, shift=[0.3, -1.0, 2.0])
+    s1, s2 = guess.pair_samples(b), guess.pair_samples(b2)
+    assert np.allclose(s1["feats"], s2["feats"], atol=1e-6)
+    D1 = guess.assemble(s1, _fake_prediction(s1["feats"]))
+    D2 = guess.assemble(s2, _fake_prediction(s2["feats"]))
+    # a density transforms contragrediently to the overlap: D2 = M^-T D1 M^-1
+    Mi = np.linalg.inv(_block_rotation(b, Q))
+    assert np.abs(Mi.T @ D1 @ Mi - D2).max() < 1e-10
+    assert np.allclose(D1, D1.T)
+
+
+def test_target_roundtrip():
+    """Targets taken from an assembled density assemble back to it."""
+    b = synth.water_cluster(2, 13)
+    s = guess.pair_samples(b)
+    D1 = guess.assemble(s, _fake_prediction(s["feats"]))
+    t = guess.pair_samples(b, D1)
+    assert np.abs(guess.assemble(s, t["target"].astype(np.float64)) - D1).max() < 1e-5   # float32 targets
+
+
+def test_cutoff_drops_far_pairs():
+    b = synth.h_chain(12, 2.0)            # 22 bohr long
+    s = guess.pair_samples(b)
+    nsh = 12
+    assert len(s["ia"]) < nsh * (nsh + 1) // 2
+    D = guess.assemble(s, np.ones((len(s["ia"]), 36)))
+    assert D[0, 11] == 0.0 and D[0, 6] != 0.0
+
+
+# ---------------------------------------------------------------------------
+# network oracle
+# ---------------------------------------------------------------------------
+
+
+def _small_net(rng, dims=((7, 11), (11, 9), (9, 5))):
+    W = [rng.standard_normal(d) * 0.5 for d in dims]
+    b = [rng.standard_normal(d[1]) * 0.1 for d in dims]
+    return W, b
+
+
+def test_mlp_oracle_gradients_by_finite_differences():
+    rng = np.random.default_rng(0)
+    W, b = _small_net(rng)
+    X = rng.standard_normal((13, 7))
+    T = rng.standard_normal((13, 5))
+    mask = (rng.random((13, 5)) < 0.7).astype(float)
+    loss, dW, db = omlp.loss_and_grads(X, T, mask, W, b)
+    h = 1e-6
+    for k in range(3):
+        for idx in [(0, 0), (2, 3), (W[k].shape[0] - 1, W[k].shape[1] - 1)]:
+            Wp = [w.copy() for w in W]
+            Wm = [w.copy() for w in W]
+            Wp[k][idx] += h
+            Wm[k][idx] -= h
+            fd = (omlp.loss_and_grads(X, T, mask, Wp, b)[0] - omlp.loss_and_grads(X, T, mask, Wm, b)[0]) / (2 * h)
+            assert abs(fd - dW[k][idx]) < 1e-7 * max(1.0, abs(fd))
+        j = b[k].shape[0] // 2
+        bp = [v.copy() for v in b]
+        bm = [v.copy() for v in b]
+        bp[k][j] += h
+        bm[k][j] -= h
+        fd = (omlp.loss_and_grads(X, T, mask, W, bp)[0] - omlp.loss_and_grads(X, T, mask, W, bm)[0]) / (2 * h)
+        assert abs(fd - db[k][j]) < 1e-7 * max(1.0, abs(fd))
+
+
+def test_mlp_oracle_loss_definition():
+    """Zero loss at T = Y; loss of a one-layer special case by hand."""
+    rng = np.random.default_rng(1)
+    W, b = _small_net(rng)
+    X = rng.standard_normal((4, 7))
+    Y = omlp.forward(X, W, b)[2]
+    mask = np.ones_like(Y)
+    assert omlp.loss_and_grads(X, Y, mask, W, b)[0] == 0.0
+    # identity-like net: ReLU of positive values is the identity
+    I7 = [np.eye(7), np.eye(7), np.eye(7)]
+    z = [np.zeros(7)] * 3
+    Xp = np.abs(X)
+    m = np.zeros((4, 7))
+    m[1, 2] = 1.0
+    m[3, 0] = 1.0
+    T = np.zeros((4, 7))
+    assert np.isclose(omlp.loss_and_grads(Xp, T, m, I7, z)[0], (Xp[1, 2] ** 2 + Xp[3, 0] ** 2) / 2)
+
+
+def test_oracle_bf16_rounding_matches_torch():
+    import torch
+    rng = np.random.default_rng(2)
+    x = np.concatenate([rng.standard_normal(5000) * 10.0 ** rng.integers(-30, 30, 5000),
+                        [0.0, -0.0, 1.0, 1.0 + 2.0 ** -8, 1.0 + 3 * 2.0 ** -8, 3.0e38, 1e-40,
+                         np.inf, -np.inf]]).astype(np.float32)
+    ref = torch.from_numpy(x).to(torch.bfloat16).float().double().numpy()
+    assert np.array_equal(omlp.round_bf16(x), ref)
+
+
+def test_oracle_bf16_forward_close_to_fp64():
+    rng = np.random.default_rng(3)
+    W, b = _small_net(rng)
+    X = rng.standard_normal((20, 7))
+    y64 = omlp.forward(X, W, b)[2]
+    y16 = omlp.forward(X, W, b, bf16=True)[2]
+    assert np.abs(y16 - y64).max() < 0.05 * np.abs(y64).max()
+    assert not np.array_equal(y16, y64)
+
+
+def test_oracle_mcweeny_fixed_point_and_quadratic_convergence():
+    b = synth.water_cluster(1, 0)
+    res = oracle.scf(b, conv_rms_dD=1e-10)
+    S = oracle.Basis(b).one_electron()[0]
+    D = res["D"]
+    D1, e0, e1 = oracle.mcweeny(D, S, 2)
+    assert e0 < 1e-8 and np.abs(D1 - D).max() < 1e-8
+    rng = np.random.default_rng(4)
+    E = rng.standard_normal(D.shape)
+    Dp = D + 1e-3 * (E + E.T)
+    errs = [oracle.mcweeny(Dp, S, k)[2] for k in range(4)]
+    assert errs[0] > 1e-4
+    for a, c in zip(errs[:2], errs[1:3]):
+        assert c < 10 * a * a + 1e-13          # quadratic
+    DN = oracle.mcweeny(Dp, S, 6)[0]
+    assert abs(np.trace(DN @ S) - b["nelec"]) < 1e-8

@@ -31,6 +31,25 @@ def log(*a):
     print("[bench]", *a, file=sys.stderr, flush=True)
 
 
+def kernel_traffic(workload, dom):
+    """HBM bytes per launch of the dominant kernel from the committed counter
+    summary (FETCH_SIZE and WRITE_SIZE runs, each scaled by the reading of a
+    plain copy of known size); None if absent or taken from other sources."""
+    path = os.path.join(ROOT, "profiles", f"k_eri_{workload}_fp64_traffic.md")
+    if not os.path.exists(path):
+        return None
+    text = open(path).read()
+    try:
+        blob = json.loads(text.split("```json")[1].split("```")[0])
+    except (IndexError, ValueError):
+        return None
+    from paper_2510_24968_amd.prof_traffic import source_digest
+    if blob.get("source_digest") != source_digest():
+        return None
+    rec = blob.get("kernels", {}).get(dom["cls"])
+    return None if rec is None else rec["bytes_per_launch"]
+
+
 def cpu_baseline(basis, w, D, target_s=15.0, seed=0):
     """Oracle (plain FP64 C, OpenMP) on a bounded random sample of the
     workload's Schwarz-kept canonical quartets, digested into J/K."""
@@ -59,15 +78,21 @@ def cpu_baseline(basis, w, D, target_s=15.0, seed=0):
     t0 = time.time()
     B.fock_jk_list(Dh, probe)
     rate = len(probe) / max(time.time() - t0, 1e-6)
-    n = int(min(50_000_000, max(20_000, rate * target_s)))
-    quartets = draw(n)
-    t0 = time.time()
-    B.fock_jk_list(Dh, quartets)
-    t = time.time() - t0
-    return {"value": n / t, "unit": "screened quartets/s", "cores": oracle.num_threads(),
+    # fresh samples until about target_s seconds of oracle work are timed
+    n_tot, t_tot = 0, 0.0
+    while t_tot < 0.9 * target_s:
+        n = int(min(50_000_000, max(20_000, rate * (target_s - t_tot))))
+        quartets = draw(n)
+        t0 = time.time()
+        B.fock_jk_list(Dh, quartets)
+        t = time.time() - t0
+        n_tot += n
+        t_tot += t
+        rate = n / max(t, 1e-6)
+    return {"value": n_tot / t_tot, "unit": "screened quartets/s", "cores": oracle.num_threads(),
             "kind": "oracle",
-            "sample": f"{n} uniformly drawn Schwarz-kept canonical quartets of the same "
-                      f"workload, digested into J/K at the core-guess density ({t:.1f} s)"}
+            "sample": f"{n_tot} uniformly drawn Schwarz-kept canonical quartets of the same "
+                      f"workload, digested into J/K at the core-guess density ({t_tot:.1f} s)"}
 
 
 def run_batch(a, basis_list, w):
@@ -206,28 +231,35 @@ def main():
     log(f"nbf={ctx.nbf} setup {t_setup:.2f}s screen {t_screen:.2f}s kept {st['quartets_kept']}"
         f" of {st['quartets_total']} (fp32 part {st['quartets_fp32']})")
 
-    def timed_steps(prec):
+    def timed_steps(prec, profile=False):
+        """K timed SCF steps; with profile, every class launch of every step is
+        bracketed by HIP events on the build stream (records per step)."""
         ctx.scf_reset()
         D = ctx.core_guess()
         for _ in range(a.warmup):
             ctx.scf_step(D, prec)
+        ctx.set_profiling(profile)
         torch.cuda.synchronize()
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         tw = time.time()
         e0.record()
         info = None
+        per_step = []
         for k in range(a.steps):
             info = ctx.scf_step(D, prec)
+            if profile:
+                per_step.append(ctx.class_profile())
             log(f"{prec} step {k + 1}/{a.steps} E={info['E_total']:.10f}")
         e1.record()
         torch.cuda.synchronize()
         wall = time.time() - tw
-        return e0.elapsed_time(e1) / a.steps, wall, info, D
+        ctx.set_profiling(False)
+        return e0.elapsed_time(e1) / a.steps, wall, info, D, per_step
 
-    ms64, wall64, info64, D64 = timed_steps("fp64")
+    ms64, wall64, info64, D64, steps_prof = timed_steps("fp64", profile=True)
     res_mixed = None
     if not a.no_mixed:
-        msmx, wallmx, infomx, Dmx = timed_steps("mixed")
+        msmx, wallmx, infomx, Dmx, _ = timed_steps("mixed")
     # Fock build alone, and the mixed-vs-FP64 energy difference, at one density
     Dfix = ctx.core_guess()
     for _ in range(2):
@@ -246,19 +278,26 @@ def main():
         times.sort()
         fb[prec] = times[len(times) // 2] / 1e3
         E[prec] = ctx.fock_build(Dfix, prec)["E_elec"]
-    # per-class kernel times of one FP64 build (HIP events on the build stream)
-    ctx.set_profiling(True)
-    ctx.fock_build(Dfix, "fp64", energy=False)
-    prof = ctx.class_profile()
+    # per-class kernel times averaged over the timed FP64 steps
+    prof = []
+    for rec in steps_prof[0]:
+        r = dict(rec)
+        r["ms"] = sum(next(x["ms"] for x in sp if x["cls"] == rec["cls"] and x["fp32"] == rec["fp32"])
+                      for sp in steps_prof) / len(steps_prof)
+        prof.append(r)
     prof_mixed = []
     if not a.no_mixed:
+        ctx.set_profiling(True)
         ctx.fock_build(Dfix, "mixed", energy=False)
         prof_mixed = ctx.class_profile()
-    ctx.set_profiling(False)
+        ctx.set_profiling(False)
     dom = max(prof, key=lambda r: r["ms"])
     achieved = dom["flops"] / (dom["ms"] * 1e-3) / 1e12
+    achieved_exec = dom["flops_exec"] / (dom["ms"] * 1e-3) / 1e12
     total_flops = sum(r["flops"] for r in prof)
+    total_exec = sum(r["flops_exec"] for r in prof)
     total_ms = sum(r["ms"] for r in prof)
+    traffic = kernel_traffic(a.workload, dom)
 
     nq = st["quartets_kept"]
     out = {
@@ -289,20 +328,26 @@ def main():
                                   "mixed_fp64": st["flops_mixed_fp64"],
                                   "mixed_fp32": st["flops_mixed_fp32"]},
         "fock_build_fp64_tflops": total_flops / (total_ms * 1e-3) / 1e12,
+        "fock_build_fp64_tflops_exec": total_exec / (total_ms * 1e-3) / 1e12,
         "roofline": {"bound": "alu", "kernel": f"k_eri {dom['cls']} fp64",
                      "achieved": achieved, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved / FP64_PEAK_TFLOPS, "traffic": None,
-                     "launch_ms": dom["ms"], "launch_flops": dom["flops"]},
+                     "frac": achieved / FP64_PEAK_TFLOPS, "traffic": traffic,
+                     "launch_ms": dom["ms"], "launch_flops": dom["flops"],
+                     "launches_timed": len(steps_prof),
+                     "achieved_exec": achieved_exec,
+                     "frac_exec": achieved_exec / FP64_PEAK_TFLOPS},
         "class_profile": [{"cls": r["cls"], "ms": round(r["ms"], 4),
                            "quartets": r["quartets"],
-                           "tflops": round(r["flops"] / max(r["ms"], 1e-9) / 1e9, 3)}
+                           "tflops": round(r["flops"] / max(r["ms"], 1e-9) / 1e9, 3),
+                           "tflops_exec": round(r["flops_exec"] / max(r["ms"], 1e-9) / 1e9, 3)}
                           for r in sorted(prof, key=lambda r: -r["ms"])],
     }
     if not a.no_mixed:
         out["class_profile_mixed"] = [
             {"cls": r["cls"] + (" f32" if r["fp32"] else " f64"), "ms": round(r["ms"], 4),
              "quartets": r["quartets"],
-             "tflops": round(r["flops"] / max(r["ms"], 1e-9) / 1e9, 3)}
+             "tflops": round(r["flops"] / max(r["ms"], 1e-9) / 1e9, 3),
+             "tflops_exec": round(r["flops_exec"] / max(r["ms"], 1e-9) / 1e9, 3)}
             for r in sorted(prof_mixed, key=lambda r: -r["ms"])]
         out["mixed"] = {"value": nq * 1e3 / msmx, "ms_per_step": msmx, "dtype": "f64+f32",
                         "dE_vs_fp64_build_Ha": E["mixed"] - E["fp64"],

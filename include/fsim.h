@@ -81,7 +81,8 @@ typedef struct {
     int64_t quartets_fp64;     /* of which evaluated in FP64 (mixed mode) */
     int64_t quartets_fp32;     /* of which evaluated in FP32 (mixed mode) */
     int64_t prim_quartets_kept;
-    double flops_fp64;         /* algorithmic flop model of one FP64-mode build */
+    double flops_fp64;         /* reference flop model (see fsim_class_profile) of
+                                  one FP64-mode build */
     double flops_mixed_fp64;   /* same, mixed mode, FP64 part */
     double flops_mixed_fp32;   /* same, mixed mode, FP32 part */
 } fsim_screen_stats;
@@ -178,8 +179,14 @@ typedef struct {
     int32_t tiles;            /* wave tiles (one bra pair x up to 64 kets) */
     int64_t quartets;         /* contracted quartets evaluated */
     int64_t prim_quartets;    /* primitive quartets */
-    double flops;             /* algorithmic flop model of the launch */
+    double flops;             /* reference flop model of the launch: per primitive
+                                 quartet 25 + 30 + 3(L+1) + 2 C(L+4,4)
+                                 + 2 C(Lab+3,3) C(Lcd+3,3) n_cart(cd), per bra
+                                 primitive pair 2 C(Lab+3,3) n_cart(ab) n_cart(cd),
+                                 per quartet 12 n_cart(abcd) (FMA = 2) */
     double ms;                /* measured kernel time */
+    double flops_exec;        /* flops the kernels execute: nonzero Hermite box
+                                 entries only, chunk recomputation not counted */
 } fsim_class_profile;
 
 /* Enable (1) or disable (0) per-launch timing of subsequent Fock builds. */
@@ -262,6 +269,16 @@ fsim_status fsim_batch_scf_info(const fsim_ctx *ctx, fsim_scf_info *info);
  * replay with events.  Rescreening drops the graphs.  enable = 0 returns to
  * direct launches. */
 fsim_status fsim_set_graph(fsim_ctx *ctx, int32_t enable);
+
+/* Digest target of the Fock build (the J' and K' half-sums of Eq. fock).
+ * enable != 0 (the default): every XCD of the GPU adds into its own private
+ * copy of J' and K' (the XCD is read from the wave's XCC_ID register) and
+ * the copies are summed after the class kernels, so that the FP64 atomics
+ * of one cache line stay within one XCD's L2.  Costs 2 x 8 x (packed matrix
+ * size) doubles of device memory, allocated on the next build.  enable = 0:
+ * one shared copy.  Results agree to rounding either way; changing the
+ * setting drops captured graphs. */
+fsim_status fsim_set_xcd_private(fsim_ctx *ctx, int32_t enable);
 
 /* McWeeny purification of a trial density of a one-molecule context: with
  * P = D/2, P <- 3 PSP - 2 PSPSP, at most iters times or until

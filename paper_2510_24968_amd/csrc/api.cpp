@@ -52,7 +52,7 @@ namespace {
 // of the mixed-mode split.
 struct ListStats {
     int64_t nq = 0, npq = 0;
-    double flops = 0.0;
+    double flops = 0.0, flops_exec = 0.0;
 };
 struct ClassLists {
     TileList all64, mix64, mix32;
@@ -137,6 +137,9 @@ struct fsim_ctx {
 
     // work buffers
     double *Jh = nullptr, *Kh = nullptr, *F = nullptr, *Dn = nullptr, *T1 = nullptr, *T2 = nullptr;
+    // per-XCD private J'/K' accumulators (NXCD copies of each), summed after the build
+    bool xcd_private = true;
+    double *priv = nullptr;
     double *eig = nullptr, *ework = nullptr, *scal = nullptr;
     int *dinfo = nullptr;
     rocblas_handle blas = nullptr;
@@ -159,6 +162,8 @@ struct fsim_ctx {
     bool have_prev = false;
     double E_prev = 0.0;
 };
+
+static void drop_graphs(fsim_ctx *c);
 
 static int ncart_h(int l) { return (l + 1) * (l + 2) / 2; }
 
@@ -753,16 +758,42 @@ extern "C" fsim_status fsim_eri_quartets(fsim_ctx *c, int64_t n, const int32_t *
 // Schwarz screening and work lists
 // ---------------------------------------------------------------------------
 
-static double flops_per_prim_quartet(int la, int lb, int lc, int ld) {
-    // algorithmic model (FMA = 2): source + Boys ~ 60 + 3(L+1), R recursion,
-    // W over ket boxes x bra Hermite set, block from bra boxes (per ket box set)
+// Flop models of one class (FMA = 2), as per-primitive-quartet,
+// per-bra-primitive-pair and per-contracted-quartet terms.
+struct FlopModel {
+    double prim, bra, quartet;
+};
+static double binom(int n, int k) {
+    double r = 1.0;
+    for (int i = 1; i <= k; ++i) r = r * (n - k + i) / i;
+    return r;
+}
+// Reference model: dense Hermite sets.  Per primitive quartet 25 (setup) +
+// 30 + 3(L+1) (Boys) + 2 C(L+4,4) (R) + 2 C(Lab+3,3) C(Lcd+3,3) n_cart(cd)
+// (step 1); per bra primitive pair 2 C(Lab+3,3) n_cart(ab) n_cart(cd)
+// (step 2); per contracted quartet 6 n_cart(abcd) FMAs of digest.
+static FlopModel flop_model(int la, int lb, int lc, int ld) {
+    const int L = la + lb + lc + ld, lab = la + lb, lcd = lc + ld;
+    const double nab = ncart_h(la) * ncart_h(lb), ncd = ncart_h(lc) * ncart_h(ld);
+    FlopModel m;
+    m.prim = 25.0 + 30.0 + 3.0 * (L + 1) + 2.0 * binom(L + 4, 4) +
+             2.0 * binom(lab + 3, 3) * binom(lcd + 3, 3) * ncd;
+    m.bra = 2.0 * binom(lab + 3, 3) * nab * ncd;
+    m.quartet = 12.0 * nab * ncd;
+    return m;
+}
+// What the kernels execute (without chunk recomputation): only the nonzero
+// Hermite box entries of each component pair, and the R recursion's own count.
+static FlopModel flop_model_exec(int la, int lb, int lc, int ld) {
     const int L = la + lb + lc + ld;
     double rec = 0;
     for (int n = 0; n < L; ++n)
         for (int s = 1; s <= L - n; ++s) rec += (s + 1) * (s + 2) / 2;
-    const double step1 = (double)n_entries(lc, ld) * nherm(la + lb);
-    const double step2 = (double)n_entries(la, lb) * ncart_h(lc) * ncart_h(ld);
-    return 60.0 + 3.0 * (L + 1) + 2.0 * rec + 2.0 * step1 + 2.0 * step2;
+    FlopModel m;
+    m.prim = 60.0 + 3.0 * (L + 1) + 2.0 * rec + 2.0 * n_entries(lc, ld) * nherm(la + lb);
+    m.bra = 2.0 * n_entries(la, lb) * ncart_h(lc) * ncart_h(ld);
+    m.quartet = 12.0 * ncart_h(la) * ncart_h(lb) * ncart_h(lc) * ncart_h(ld);
+    return m;
 }
 
 static fsim_status upload_list(DevPool &pool, TileList &tl, const std::vector<int> &bra,
@@ -849,11 +880,7 @@ extern "C" fsim_status fsim_schwarz_screen(fsim_ctx *c, double tau, double tau32
     }
     // kept pairs per class, ordered by (molecule, Q descending); each
     // molecule owns a contiguous segment of every class table
-    for (int p = 0; p < 2; ++p)
-        if (c->gexec[p]) {
-            hipGraphExecDestroy(c->gexec[p]);
-            c->gexec[p] = nullptr;
-        }
+    drop_graphs(c);
     c->screen_pool.clear();
     c->screened = false;
     fsim_screen_stats S{};
@@ -900,7 +927,7 @@ extern "C" fsim_status fsim_schwarz_screen(fsim_ctx *c, double tau, double tau32
             const auto &Qb = c->Qkept[X], &Qk = c->Qkept[Y];
             std::vector<int> b64, lo64, hi64, bm64, lom64, him64, bm32, lom32, him32;
             const int la = pclass_l1(X), lb = pclass_l2(X), lc = pclass_l1(Y), ld = pclass_l2(Y);
-            const double fpq = flops_per_prim_quartet(la, lb, lc, ld);
+            const FlopModel fm = flop_model(la, lb, lc, ld), fx = flop_model_exec(la, lb, lc, ld);
             for (int i = 0; i < (int)Qb.size(); ++i) {
                 const double qi = Qb[i];
                 const int m = kmol[X][i];
@@ -955,27 +982,26 @@ extern "C" fsim_status fsim_schwarz_screen(fsim_ctx *c, double tau, double tau32
             std::vector<long long> kpre(kk.size() + 1, 0);
             for (size_t j = 0; j < kk.size(); ++j) kpre[j + 1] = kpre[j] + kk[j];
             cl.s64 = cl.sm64 = cl.sm32 = ListStats{};
-            for (size_t t = 0; t < b64.size(); ++t) {
-                const long long pq = (long long)kb[b64[t]] * (kpre[hi64[t]] - kpre[lo64[t]]);
-                S.prim_quartets_kept += pq;
-                S.flops_fp64 += fpq * pq;
-                cl.s64.npq += pq;
-                cl.s64.flops += fpq * pq;
-            }
+            auto tally = [&](ListStats &ls, const std::vector<int> &bb, const std::vector<int> &lo,
+                             const std::vector<int> &hi) {
+                for (size_t t = 0; t < bb.size(); ++t) {
+                    const long long nk = hi[t] - lo[t];
+                    const long long pq = (long long)kb[bb[t]] * (kpre[hi[t]] - kpre[lo[t]]);
+                    const double bp = (double)kb[bb[t]] * nk;   // bra primitive pairs x kets
+                    ls.npq += pq;
+                    ls.flops += fm.prim * pq + fm.bra * bp + fm.quartet * nk;
+                    ls.flops_exec += fx.prim * pq + fx.bra * bp + fx.quartet * nk;
+                }
+            };
+            tally(cl.s64, b64, lo64, hi64);
+            tally(cl.sm64, bm64, lom64, him64);
+            tally(cl.sm32, bm32, lom32, him32);
+            S.prim_quartets_kept += cl.s64.npq;
+            S.flops_fp64 += cl.s64.flops;
+            S.flops_mixed_fp64 += cl.sm64.flops;
+            S.flops_mixed_fp32 += cl.sm32.flops;
             cl.s64.nq = cl.all64.nquartet;
-            for (size_t t = 0; t < bm64.size(); ++t) {
-                const long long pq = (long long)kb[bm64[t]] * (kpre[him64[t]] - kpre[lom64[t]]);
-                S.flops_mixed_fp64 += fpq * pq;
-                cl.sm64.npq += pq;
-                cl.sm64.flops += fpq * pq;
-            }
             cl.sm64.nq = cl.mix64.nquartet;
-            for (size_t t = 0; t < bm32.size(); ++t) {
-                const long long pq = (long long)kb[bm32[t]] * (kpre[him32[t]] - kpre[lom32[t]]);
-                S.flops_mixed_fp32 += fpq * pq;
-                cl.sm32.npq += pq;
-                cl.sm32.flops += fpq * pq;
-            }
             cl.sm32.nq = cl.mix32.nquartet;
         }
     if (tau32 <= 0) {
@@ -999,12 +1025,31 @@ extern "C" fsim_status fsim_schwarz_screen(fsim_ctx *c, double tau, double tau32
 // Enqueue the class kernels and the Fock assembly for density D into F (J, K
 // optional) on stream s.  No host synchronisation, no memset: this is the
 // sequence a graph captures.
+// Captured Fock builds bake in kernel variants and buffers: drop them when
+// either changes.
+static void drop_graphs(fsim_ctx *c) {
+    for (int p = 0; p < 2; ++p)
+        if (c->gexec[p]) {
+            hipGraphExecDestroy(c->gexec[p]);
+            c->gexec[p] = nullptr;
+        }
+}
+
+static constexpr int NXCD = 8;   // XCDs of an MI355X
+
 static fsim_status enqueue_build(fsim_ctx *c, const double *D, double *F, double *J, double *K,
                                  bool mixed, std::vector<fsim_class_profile> *prof,
                                  hipStream_t s) {
     const size_t P = (size_t)c->packed;
-    HIPCHK(fill(c->Jh, P, 0.0, s));
-    HIPCHK(fill(c->Kh, P, 0.0, s));
+    const bool xp = c->xcd_private && c->priv;
+    double *Jacc = xp ? c->priv : c->Jh;
+    double *Kacc = xp ? c->priv + NXCD * P : c->Kh;
+    if (xp) {
+        HIPCHK(fill(c->priv, 2 * NXCD * P, 0.0, s));
+    } else {
+        HIPCHK(fill(c->Jh, P, 0.0, s));
+        HIPCHK(fill(c->Kh, P, 0.0, s));
+    }
     int nev = 0;
     // heaviest classes (highest L) first
     for (int X = NPCLASS - 1; X >= 0; --X)
@@ -1023,6 +1068,7 @@ static fsim_status enqueue_build(fsim_ctx *c, const double *D, double *F, double
                     pr.quartets = ls.nq;
                     pr.prim_quartets = ls.npq;
                     pr.flops = ls.flops;
+                    pr.flops_exec = ls.flops_exec;
                     prof->push_back(pr);
                     HIPCHK(hipEventRecord(c->ev[nev++], s));
                 }
@@ -1032,8 +1078,9 @@ static fsim_status enqueue_build(fsim_ctx *c, const double *D, double *F, double
                 a.same_class = X == Y;
                 a.tl = tl;
                 a.D = D;
-                a.Jh = c->Jh;
-                a.Kh = c->Kh;
+                a.Jh = Jacc;
+                a.Kh = Kacc;
+                a.xcd_stride = xp ? (long long)P : 0;
                 a.nbf = c->nbf;
                 a.mol_off = c->d_mol_off;
                 a.mol_n = c->d_mol_n;
@@ -1043,6 +1090,10 @@ static fsim_status enqueue_build(fsim_ctx *c, const double *D, double *F, double
                 if (prof) HIPCHK(hipEventRecord(c->ev[nev++], s));
             }
         }
+    if (xp) {
+        HIPCHK(sum_copies(P, NXCD, c->priv, P, c->Jh, s));
+        HIPCHK(sum_copies(P, NXCD, c->priv + NXCD * P, P, c->Kh, s));
+    }
     HIPCHK(assemble_fock_packed(layout_of(c), c->Jh, c->Kh, c->H, F, J, K, s));
     return FSIM_OK;
 }
@@ -1057,6 +1108,7 @@ static fsim_status fock_build(fsim_ctx *c, const double *D, double *F, double *J
         c->ev.resize(2 * 2 * NPCLASS * NPCLASS);
         for (auto &e : c->ev) HIPCHK(hipEventCreate(&e));
     }
+    if (c->xcd_private && !c->priv) HIPCHK(c->pool.alloc(&c->priv, 2 * NXCD * P));
     const bool use_graph = c->graph_enabled && !c->profiling && !J && !K && F;
     if (use_graph) {
         const int g = mixed ? 1 : 0;
@@ -1158,6 +1210,14 @@ extern "C" fsim_status fsim_set_tuning(fsim_ctx *c, const fsim_tuning *t, int32_
         c->wpb[r.bra_class][r.ket_class][r.fp32] = r.waves_per_block;
         c->tuned_ms[r.bra_class][r.ket_class][r.fp32] = r.ms;
     }
+    drop_graphs(c);
+    return FSIM_OK;
+}
+
+extern "C" fsim_status fsim_set_xcd_private(fsim_ctx *c, int32_t enable) {
+    if (!c) return fail(FSIM_EINVAL, "NULL argument");
+    c->xcd_private = enable != 0;
+    drop_graphs(c);
     return FSIM_OK;
 }
 
@@ -1240,6 +1300,7 @@ extern "C" fsim_status fsim_autotune(fsim_ctx *c, const double *D, fsim_precisio
                 if (best[X][Y][f] < 1e299) c->tuned_ms[X][Y][f] = best[X][Y][f];
             }
     c->profiling = was;
+    drop_graphs(c);
     return st;
 }
 

@@ -46,6 +46,12 @@ __device__ __forceinline__ const double *etab<double>(const PairTable &t) { retu
 template <>
 __device__ __forceinline__ const float *etab<float>(const PairTable &t) { return t.Ef; }
 
+// Index (0..7) of the XCD the calling wave runs on, from the XCC_ID
+// hardware register (bits 3:0).
+__device__ __forceinline__ int xcd_index() {
+    return __builtin_amdgcn_s_getreg((3 << 11) | (0 << 6) | 20) & 7;
+}
+
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
@@ -162,6 +168,8 @@ __global__ __launch_bounds__(256) void k_eri_lane(EriArgs a) {
     const T *__restrict__ Eb = etab<T>(a.bra);
     const T *__restrict__ Ek = etab<T>(a.ket);
     const size_t nb = a.bra.n, nk = a.ket.n;
+    // per-XCD private J'/K' copies keep each cache line's atomics on one XCD
+    const long long xoff = (!STORE && a.xcd_stride) ? xcd_index() * a.xcd_stride : 0;
 
     for (int tile0 = blockIdx.x * wpb + (threadIdx.x >> 6); tile0 < ntile;
          tile0 += gridDim.x * wpb) {
@@ -188,8 +196,8 @@ __global__ __launch_bounds__(256) void k_eri_lane(EriArgs a) {
         const long long mbase = STORE ? 0 : a.mol_off[mol];
         const int N = STORE ? 0 : a.mol_n[mol];
         const double *__restrict__ D = STORE ? nullptr : a.D + mbase;
-        double *__restrict__ Jh = STORE ? nullptr : a.Jh + mbase;
-        double *__restrict__ Kh = STORE ? nullptr : a.Kh + mbase;
+        double *__restrict__ Jh = STORE ? nullptr : a.Jh + xoff + mbase;
+        double *__restrict__ Kh = STORE ? nullptr : a.Kh + xoff + mbase;
         int f1 = 0, f2 = 0, f3 = 0, f4 = 0;
         double fac = 0.0;
         long long soff = 0;
@@ -625,8 +633,9 @@ __global__ __launch_bounds__(64) void k_eri_wave(EriArgs a) {
                 const long long mbase = a.mol_off[mol];
                 const int N = a.mol_n[mol];
                 const double *__restrict__ D = a.D + mbase;
-                double *__restrict__ Jh = a.Jh + mbase;
-                double *__restrict__ Kh = a.Kh + mbase;
+                const long long xoff = a.xcd_stride ? xcd_index() * a.xcd_stride : 0;
+                double *__restrict__ Jh = a.Jh + xoff + mbase;
+                double *__restrict__ Kh = a.Kh + xoff + mbase;
                 const int f1 = a.bra.bf1[bra], f2 = a.bra.bf2[bra];
                 const int f3 = a.ket.bf1[ket], f4 = a.ket.bf2[ket];
                 double fac = 1.0;

@@ -147,6 +147,9 @@ struct EriArgs {
     const double *D;        // packed per-molecule blocks (one block for a single molecule)
     double *Jh;
     double *Kh;
+    // > 0: Jh and Kh each hold one copy per XCD, xcd_stride elements apart,
+    // and a wave adds into the copy of the XCD it runs on (0: one copy)
+    long long xcd_stride;
     int nbf;
     const long long *mol_off;   // [nmol] offset of each molecule's N_m x N_m block
     const int *mol_n;           // [nmol] N_m

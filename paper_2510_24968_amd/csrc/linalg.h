@@ -14,6 +14,9 @@ struct DiisPtrs {
 };
 
 hipError_t fill(double *x, size_t n, double v, hipStream_t s);
+// dst[i] = sum_{k < ncopy} src[k * stride + i] for i < n
+hipError_t sum_copies(size_t n, int ncopy, const double *src, size_t stride, double *dst,
+                      hipStream_t s);
 hipError_t assemble_fock(int N, const double *Jh, const double *Kh, const double *H, double *F,
                          double *J, double *K, hipStream_t s);
 hipError_t dot3(size_t n, const double *A, const double *B, const double *C, double w, double *out,

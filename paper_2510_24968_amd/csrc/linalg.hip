@@ -9,6 +9,16 @@ __global__ void k_fill(double *x, size_t n, double v) {
         x[i] = v;
 }
 
+__global__ void k_sum_copies(size_t n, int ncopy, const double *__restrict__ src, size_t stride,
+                             double *dst) {
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n;
+         i += (size_t)gridDim.x * blockDim.x) {
+        double v = 0.0;
+        for (int k = 0; k < ncopy; ++k) v += src[k * stride + i];
+        dst[i] = v;
+    }
+}
+
 // J = J' + J'^T, K = K' + K'^T, F = H + J - K/2 (Eq. fock, G = J - K/2).
 __global__ void k_assemble_fock(int N, const double *__restrict__ Jh, const double *__restrict__ Kh,
                                 const double *__restrict__ H, double *F, double *J, double *K) {
@@ -327,6 +337,11 @@ static inline dim3 grid_for(size_t n) {
 
 hipError_t fill(double *x, size_t n, double v, hipStream_t s) {
     hipLaunchKernelGGL(k_fill, grid_for(n), dim3(256), 0, s, x, n, v);
+    return hipGetLastError();
+}
+hipError_t sum_copies(size_t n, int ncopy, const double *src, size_t stride, double *dst,
+                      hipStream_t s) {
+    hipLaunchKernelGGL(k_sum_copies, grid_for(n), dim3(256), 0, s, n, ncopy, src, stride, dst);
     return hipGetLastError();
 }
 hipError_t assemble_fock(int N, const double *Jh, const double *Kh, const double *H, double *F,

@@ -60,7 +60,8 @@ class _ClassProfile(ctypes.Structure):
     _fields_ = [("bra_class", ctypes.c_int32), ("ket_class", ctypes.c_int32),
                 ("fp32", ctypes.c_int32), ("tiles", ctypes.c_int32),
                 ("quartets", ctypes.c_int64), ("prim_quartets", ctypes.c_int64),
-                ("flops", ctypes.c_double), ("ms", ctypes.c_double)]
+                ("flops", ctypes.c_double), ("ms", ctypes.c_double),
+                ("flops_exec", ctypes.c_double)]
 
 
 class _Tuning(ctypes.Structure):
@@ -108,6 +109,7 @@ def lib():
         "fsim_batch_energies": [vp, vp],
         "fsim_batch_scf_info": [vp, vp],
         "fsim_set_graph": [vp, i32],
+        "fsim_set_xcd_private": [vp, i32],
         "fsim_set_tuning": [vp, vp, i32],
         "fsim_get_tuning": [vp, vp, i32, ctypes.POINTER(i32)],
         "fsim_autotune": [vp, vp, ctypes.c_int, vp],
@@ -233,6 +235,10 @@ class Context:
         _check(lib().fsim_scf_step(self.h, _ptr(D), ctypes.byref(info), _PREC[precision],
                                    _stream()))
         return _struct_dict(info)
+
+    def set_xcd_private(self, enable=True):
+        """Per-XCD private J'/K' accumulators (default on) or one shared copy."""
+        _check(lib().fsim_set_xcd_private(self.h, 1 if enable else 0))
 
     def set_profiling(self, enable=True):
         _check(lib().fsim_set_profiling(self.h, 1 if enable else 0))

@@ -556,13 +556,31 @@ def main():
     t1 = time.time()
     hist = net.train(X, T, M, epochs=a.epochs, log=log)
     torch.cuda.synchronize()
-    log(f"training {time.time() - t1:.1f} s")
+    t_train = time.time() - t1
+    log(f"training {t_train:.1f} s")
     np.savez(os.path.join(a.out, "guess_weights.npz"), **net.state())
+    # inference throughput of the three BF16 GEMMs over the training samples
+    Xd = net.to_bf16(torch.as_tensor(X, device=net.dev))
+    nrow = (Xd.shape[0] // 65536) * 65536 or Xd.shape[0]
+    chunks = [Xd[i:i + 65536] for i in range(0, nrow, 65536)]
+    net.forward(chunks[0])
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for c in chunks:
+        net.forward(c)
+    e1.record()
+    torch.cuda.synchronize()
+    sec = e0.elapsed_time(e1) / 1e3
+    flops = 2.0 * nrow * sum(i * o for i, o in GuessNet.dims)
+    fwd = {"rows": nrow, "seconds": sec, "TFLOP/s": flops / sec / 1e12}
+    log(f"forward over {nrow} pairs: {sec * 1e3:.2f} ms, {fwd['TFLOP/s']:.1f} TFLOP/s (BF16)")
     ev = [synth.water_cluster(32, 6_000_000 + i) for i in range(a.eval)]
     res = evaluate(net, ev, log=log)
     res["loss"] = hist
     res["train_molecules"] = len(mols)
     res["train_samples"] = int(X.shape[0])
+    res["forward"] = fwd
+    res["train_seconds"] = t_train
     with open(os.path.join(a.out, "guess_eval.json"), "w") as f:
         json.dump(res, f, indent=1)
 

@@ -1,0 +1,52 @@
+"""Short driver for hardware-counter runs under rocprofv3.
+
+One FP64 (or mixed) Fock build of a named workload with its committed
+autotuner settings, preceded by a plain device copy of a known size whose
+FETCH_SIZE / WRITE_SIZE readings calibrate the HBM byte counters:
+
+    rocprofv3 --pmc FETCH_SIZE --output-format csv -d OUT -- \\
+        python3 -m paper_2510_24968_amd.prof_run --workload water64
+"""
+
+import argparse
+import os
+import time
+
+COPY_BYTES = 1 << 30
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--workload", default="water64")
+    ap.add_argument("--precision", default="fp64", choices=("fp64", "mixed"))
+    ap.add_argument("--builds", type=int, default=1)
+    a = ap.parse_args()
+    import torch
+    import synth
+    from paper_2510_24968_amd import autotune, fsim
+    log = lambda s: print(f"[prof_run] {s}", flush=True)
+    src = torch.empty(COPY_BYTES // 8, dtype=torch.float64, device="cuda").fill_(1.0)
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    dst.copy_(src)                       # the calibration copy: 1 GiB read, 1 GiB written
+    torch.cuda.synchronize()
+    log(f"calibration copy of {COPY_BYTES} bytes done")
+    del src, dst
+    basis, w = synth.workload(a.workload)
+    ctx = fsim.Context(basis, tau=w["tau"], tau_fp32=w["tau_fp32"] if w["tau_fp32"] > 0 else 1e-5)
+    ctx.schwarz_screen()
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuning",
+                        f"{a.workload}_mi355x.json")
+    if os.path.exists(path):
+        log(f"applied {autotune.apply(ctx, autotune.load(path))} tuned class settings")
+    D = ctx.core_guess()
+    for k in range(a.builds):
+        t0 = time.time()
+        ctx.fock_build(D, a.precision, energy=False)
+        torch.cuda.synchronize()
+        log(f"{a.precision} Fock build {k + 1}/{a.builds}: {time.time() - t0:.2f} s")
+    ctx.close()
+
+
+if __name__ == "__main__":
+    main()

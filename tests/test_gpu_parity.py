@@ -170,6 +170,25 @@ def test_jk_screened_counts_and_values():
     assert np.max(np.abs(r["K"].cpu().numpy() - Ko)) < 1e-11
 
 
+@pytest.mark.parametrize("private", [False, True])
+def test_jk_shared_and_xcd_private_accumulators(private):
+    """Both digest targets (one shared J'/K' or a private copy per XCD,
+    summed afterwards) give the oracle's J and K; graphs replay either."""
+    b = synth.water_cluster(3, 5)
+    ctx = _ctx(b)
+    ctx.set_xcd_private(private)
+    ctx.schwarz_screen(tau=1e-12)
+    D = _random_density(ctx.nbf, 9)
+    Jo, Ko = oracle.Basis(b).fock_jk(D, tau=1e-12)
+    r = ctx.fock_build(_dev(D), want_jk=True)
+    assert np.max(np.abs(r["J"].cpu().numpy() - Jo)) < 1e-11
+    assert np.max(np.abs(r["K"].cpu().numpy() - Ko)) < 1e-11
+    ctx.set_xcd_private(not private)
+    r2 = ctx.fock_build(_dev(D), want_jk=True)
+    assert np.max(np.abs(r2["J"].cpu().numpy() - Jo)) < 1e-11
+    assert np.max(np.abs(r2["F"].cpu().numpy() - r["F"].cpu().numpy())) < 1e-11
+
+
 def test_water10_jk_sampled_elements():
     b, w = synth.workload("water10")
     ctx = _ctx(b, tau=w["tau"])

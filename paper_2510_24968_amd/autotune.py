@@ -19,8 +19,11 @@ def cache_key(rec):
     return f"{rec['cls']}|{prec}|K{rec['kbra']}x{rec['kket']}"
 
 
-def tune(ctx, D, precisions=("fp64", "mixed")):
-    """Run the search for each precision; returns {key: record}."""
+def tune(ctx, D, precisions=("mixed", "fp64")):
+    """Run the search for each precision; returns {key: record}.  FP32
+    settings come from the mixed build and FP64 settings from the FP64
+    build (whose FP64 lists hold every kept quartet, not only the mixed
+    build's FP64 part); the context ends with the combined settings."""
     table = {}
     for prec in precisions:
         print(f"[autotune] {prec}: searching variants x waves-per-block", file=sys.stderr,
@@ -29,10 +32,11 @@ def tune(ctx, D, precisions=("fp64", "mixed")):
         recs = ctx.autotune(D, prec)
         print(f"[autotune] {prec}: done in {time.time() - t0:.1f}s", file=sys.stderr, flush=True)
         for rec in recs:
-            if rec["ms"] > 0:
+            if rec["ms"] > 0 and bool(rec["fp32"]) == (prec == "mixed"):
                 table[cache_key(rec)] = {k: rec[k] for k in
                                          ("cls", "bra_class", "ket_class", "fp32", "variant",
                                           "waves_per_block", "kbra", "kket", "ms")}
+    apply(ctx, table)
     return table
 
 

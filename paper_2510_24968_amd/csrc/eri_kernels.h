@@ -152,14 +152,23 @@ __host__ __device__ constexpr int n_chunks(int la, int lb, int lc, int ld, int l
     return ((ncart(la) + ca - 1) / ca) * ((ncart(lc) * ncart(ld) + cdc - 1) / cdc);
 }
 
+// Minimum waves per SIMD the lane kernel is compiled for.  d bras with a
+// live set of up to 128 FP64 values are held to two resident waves (256
+// registers each); every other kernel is left to the compiler, which
+// measured faster for the s and p bras.
+__host__ __device__ constexpr int lane_min_waves(int la, int lb, int lc, int ld, int ca, int cdc) {
+    return la == 2 && lane_live(la, lb, lc, ld, ca, cdc) <= 128 ? 2 : 1;
+}
+
 template <int LA, int LB, int LC, int LD, typename T, bool STORE, int CA, int CDC>
-__global__ __launch_bounds__(256) void k_eri_lane(EriArgs a) {
+__global__ __launch_bounds__(256, lane_min_waves(LA, LB, LC, LD, CA, CDC)) void k_eri_lane(EriArgs a) {
     constexpr int L = LA + LB + LC + LD, LAB = LA + LB;
     constexpr int NA = ncart(LA), NB = ncart(LB), NC = ncart(LC), ND = ncart(LD);
     constexpr int NCD = NC * ND, NHAB = nherm(LAB), NH = nherm(L);
     constexpr int NEB = n_entries(LA, LB), NEK = n_entries(LC, LD);
     constexpr int NCHA = (NA + CA - 1) / CA, NCHCD = (NCD + CDC - 1) / CDC;
     __shared__ double tab[BOYS_LDS];
+    extern __shared__ __align__(16) unsigned char stage_lds[];
     boys_stage(tab, a.boys, L);
     __syncthreads();
     const int lane = threadIdx.x & 63;
@@ -168,6 +177,28 @@ __global__ __launch_bounds__(256) void k_eri_lane(EriArgs a) {
     const T *__restrict__ Eb = etab<T>(a.bra);
     const T *__restrict__ Ek = etab<T>(a.ket);
     const size_t nb = a.bra.n, nk = a.ket.n;
+    // The bra pair is the same for the whole wave.  For d bras (large Hermite
+    // boxes, re-read in every chunk) its primitive data are copied once per
+    // tile (or per group of ks primitive pairs) into this wave's LDS slice and
+    // read back as broadcasts; s and p bras read them from global memory,
+    // which measured faster for their small boxes.
+    constexpr bool STAGE = LA == 2;
+    const int ks = STAGE ? a.stage_prims : 1 << 20;
+    double *__restrict__ sp = (double *)(stage_lds + (size_t)(threadIdx.x >> 6) * a.stage_bytes);
+    T *__restrict__ se = (T *)(sp + 4 * ks);
+    auto stage = [&](int bra_, int i0, int cnt) {
+        for (int x = lane; x < cnt * 4; x += 64) {
+            const int s = x >> 2, f = x & 3;
+            sp[x] = f == 0 ? a.bra.p[(size_t)(i0 + s) * nb + bra_]
+                           : a.bra.P[((size_t)(i0 + s) * 3 + f - 1) * nb + bra_];
+        }
+        for (int x = lane; x < cnt * NEB; x += 64)
+            se[x] = Eb[((size_t)i0 * NEB + x) * nb + bra_];
+        // the wave's own LDS writes complete before its reads
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    };
     // per-XCD private J'/K' copies keep each cache line's atomics on one XCD
     const long long xoff = (!STORE && a.xcd_stride) ? xcd_index() * a.xcd_stride : 0;
 
@@ -191,6 +222,8 @@ __global__ __launch_bounds__(256) void k_eri_lane(EriArgs a) {
         }
         const int nbp = __builtin_amdgcn_readfirstlane(a.bra.nprim[bra]);
         const int nkp = active ? a.ket.nprim[ket] : 0;
+        const bool all_staged = nbp <= ks;
+        if (STAGE && all_staged) stage(bra, 0, nbp);
         // the quartet's molecule block (bra and ket pairs share the molecule)
         const int mol = __builtin_amdgcn_readfirstlane(a.bra.mol[bra]);
         const long long mbase = STORE ? 0 : a.mol_off[mol];
@@ -234,20 +267,35 @@ __global__ __launch_bounds__(256) void k_eri_lane(EriArgs a) {
                 for (int y = 0; y < NCDc; ++y) out[x][y] = T(0);
 
             for (int i = 0; i < nbp; ++i) {
-                const double p = a.bra.p[i * nb + bra];
-                const double Px = a.bra.P[(i * 3 + 0) * nb + bra];
-                const double Py = a.bra.P[(i * 3 + 1) * nb + bra];
-                const double Pz = a.bra.P[(i * 3 + 2) * nb + bra];
+                int il = i;
+                if (STAGE && !all_staged) {
+                    il = i % ks;
+                    if (il == 0) stage(bra, i, nbp - i < ks ? nbp - i : ks);
+                }
+                const double p = STAGE ? sp[il * 4 + 0] : a.bra.p[(size_t)i * nb + bra];
+                const double Px = STAGE ? sp[il * 4 + 1] : a.bra.P[((size_t)i * 3 + 0) * nb + bra];
+                const double Py = STAGE ? sp[il * 4 + 2] : a.bra.P[((size_t)i * 3 + 1) * nb + bra];
+                const double Pz = STAGE ? sp[il * 4 + 3] : a.bra.P[((size_t)i * 3 + 2) * nb + bra];
                 T W[NCDc][NHAB];
 #pragma unroll
                 for (int x = 0; x < NCDc; ++x)
 #pragma unroll
                     for (int h = 0; h < NHAB; ++h) W[x][h] = T(0);
+                // d bras: ket primitive data loaded one primitive ahead of use
+                // (s and p bras load them in place, which measured faster)
+                double qn = 0.0, Kxn = 0.0, Kyn = 0.0, Kzn = 0.0;
+                auto kload = [&](int j_) {
+                    qn = a.ket.p[(size_t)j_ * nk + ket];
+                    Kxn = a.ket.P[((size_t)j_ * 3 + 0) * nk + ket];
+                    Kyn = a.ket.P[((size_t)j_ * 3 + 1) * nk + ket];
+                    Kzn = a.ket.P[((size_t)j_ * 3 + 2) * nk + ket];
+                };
+                if (STAGE && nkp > 0) kload(0);
                 for (int j = 0; j < nkp; ++j) {
-                    const double q = a.ket.p[j * nk + ket];
-                    const double X = Px - a.ket.P[(j * 3 + 0) * nk + ket];
-                    const double Y = Py - a.ket.P[(j * 3 + 1) * nk + ket];
-                    const double Z = Pz - a.ket.P[(j * 3 + 2) * nk + ket];
+                    if (!STAGE) kload(j);
+                    const double q = qn;
+                    const double X = Px - Kxn, Y = Py - Kyn, Z = Pz - Kzn;
+                    if (STAGE && j + 1 < nkp) kload(j + 1);
                     // 1/sqrt(p+q) once; 1/(p+q) and alpha = pq/(p+q) from it
                     const double rs = rsqrt(p + q);
                     const double alpha = p * q * (rs * rs);
@@ -290,7 +338,8 @@ __global__ __launch_bounds__(256) void k_eri_lane(EriArgs a) {
                     });
                 }
                 // bra contraction, once per bra primitive pair
-                const T *__restrict__ eb = Eb + (size_t)i * NEB * nb + bra;
+                const T *__restrict__ eb = STAGE ? se + il * NEB : Eb + (size_t)i * NEB * nb + bra;
+                const size_t es = STAGE ? 1 : nb;
                 static_for<NABc>([&](auto abl_) {
                     constexpr int abl = decltype(abl_)::value;
                     constexpr int ab = (A0 + abl / NB) * NB + abl % NB;
@@ -304,7 +353,7 @@ __global__ __launch_bounds__(256) void k_eri_lane(EriArgs a) {
                             static_for<az + 1>([&](auto v_) {
                                 constexpr int v = decltype(v_)::value;
                                 constexpr int e = ao + (t * (ay + 1) + u) * (az + 1) + v;
-                                const T ebv = eb[(size_t)e * nb];
+                                const T ebv = eb[e * es];
                                 static_for<NCDc>([&](auto cdl_) {
                                     constexpr int cdl = decltype(cdl_)::value;
                                     out[abl][cdl] = fma(ebv, W[cdl][hidx(t, u, v)], out[abl][cdl]);
@@ -458,6 +507,14 @@ __global__ __launch_bounds__(64) void k_eri_wave(EriArgs a) {
     __shared__ T rbuf[2][NH];
     __shared__ T wl[NW];
     __shared__ T ebl[NEB], ekl[NEK];
+    // digest staging: density elements D_ab, D_cd, D_bd, D_ad, D_bc, D_ac
+    // (offsets DO_*) and the J'/K' targets (offsets TG_*)
+    constexpr int DO_CD = NAB, DO_BD = DO_CD + NCD, DO_AD = DO_BD + NB * ND,
+                  DO_BC = DO_AD + NA * ND, DO_AC = DO_BC + NB * NC, NDEN = DO_AC + NA * NC;
+    constexpr int TG_JCD = NAB, TG_KAC = TG_JCD + NCD, TG_KBC = TG_KAC + NA * NC,
+                  TG_KAD = TG_KBC + NB * NC, TG_KBD = TG_KAD + NA * ND, NTGT = TG_KBD + NB * ND;
+    __shared__ double blk[STORE ? 1 : NO];
+    __shared__ double den[STORE ? 1 : NDEN];
     boys_stage(tab, a.boys, L);
     const int lane = threadIdx.x;
 
@@ -642,20 +699,68 @@ __global__ __launch_bounds__(64) void k_eri_wave(EriArgs a) {
                 if (a.bra.sh1[bra] == a.bra.sh2[bra]) fac *= 0.5;
                 if (a.ket.sh1[ket] == a.ket.sh2[ket]) fac *= 0.5;
                 if (a.same_class && ket == bra) fac *= 0.5;
+                // Reduce before scattering: the scaled block and the density
+                // elements it meets go to LDS, then every J'/K' target element
+                // is summed once and added with a single atomic (adding each
+                // block element separately would put up to NCD lanes of one
+                // instruction on the same address).
 #pragma unroll
-                for (int k = 0; k < NOL; ++k) {
-                    if (lane + 64 * k < NO) {
-                        const size_t I = f1 + oab[k] / NB, J = f2 + oab[k] % NB,
-                                     K = f3 + ocd[k] / ND, M = f4 + ocd[k] % ND;
-                        const double v = fac * (double)o[k];
-                        atomicAdd(&Jh[I * N + J], 2.0 * v * D[K * N + M]);
-                        atomicAdd(&Jh[K * N + M], 2.0 * v * D[I * N + J]);
-                        atomicAdd(&Kh[I * N + K], v * D[J * N + M]);
-                        atomicAdd(&Kh[J * N + K], v * D[I * N + M]);
-                        atomicAdd(&Kh[I * N + M], v * D[J * N + K]);
-                        atomicAdd(&Kh[J * N + M], v * D[I * N + K]);
+                for (int k = 0; k < NOL; ++k)
+                    if (lane + 64 * k < NO) blk[lane + 64 * k] = fac * (double)o[k];
+                for (int x = lane; x < NDEN; x += 64) {
+                    size_t r, c;
+                    if (x < DO_CD) { r = f1 + x / NB; c = f2 + x % NB; }
+                    else if (x < DO_BD) { r = f3 + (x - DO_CD) / ND; c = f4 + (x - DO_CD) % ND; }
+                    else if (x < DO_AD) { r = f2 + (x - DO_BD) / ND; c = f4 + (x - DO_BD) % ND; }
+                    else if (x < DO_BC) { r = f1 + (x - DO_AD) / ND; c = f4 + (x - DO_AD) % ND; }
+                    else if (x < DO_AC) { r = f2 + (x - DO_BC) / NC; c = f3 + (x - DO_BC) % NC; }
+                    else { r = f1 + (x - DO_AC) / NC; c = f3 + (x - DO_AC) % NC; }
+                    den[x] = D[r * N + c];
+                }
+                __syncthreads();
+                for (int t = lane; t < NTGT; t += 64) {
+                    double sum = 0.0;
+                    size_t r, c;
+                    if (t < TG_JCD) {   // J'_ab += 2 sum_cd v D_cd
+                        for (int cd = 0; cd < NCD; ++cd) sum += blk[t * NCD + cd] * den[DO_CD + cd];
+                        sum *= 2.0;
+                        r = f1 + t / NB;
+                        c = f2 + t % NB;
+                        atomicAdd(&Jh[r * N + c], sum);
+                    } else if (t < TG_KAC) {   // J'_cd += 2 sum_ab v D_ab
+                        const int cd = t - TG_JCD;
+                        for (int ab = 0; ab < NAB; ++ab) sum += blk[ab * NCD + cd] * den[ab];
+                        sum *= 2.0;
+                        r = f3 + cd / ND;
+                        c = f4 + cd % ND;
+                        atomicAdd(&Jh[r * N + c], sum);
+                    } else if (t < TG_KBC) {   // K'_ac += sum_bd v D_bd
+                        const int ia = (t - TG_KAC) / NC, ic = (t - TG_KAC) % NC;
+                        for (int ib = 0; ib < NB; ++ib)
+                            for (int id = 0; id < ND; ++id)
+                                sum += blk[(ia * NB + ib) * NCD + ic * ND + id] * den[DO_BD + ib * ND + id];
+                        atomicAdd(&Kh[(size_t)(f1 + ia) * N + f3 + ic], sum);
+                    } else if (t < TG_KAD) {   // K'_bc += sum_ad v D_ad
+                        const int ib = (t - TG_KBC) / NC, ic = (t - TG_KBC) % NC;
+                        for (int ia = 0; ia < NA; ++ia)
+                            for (int id = 0; id < ND; ++id)
+                                sum += blk[(ia * NB + ib) * NCD + ic * ND + id] * den[DO_AD + ia * ND + id];
+                        atomicAdd(&Kh[(size_t)(f2 + ib) * N + f3 + ic], sum);
+                    } else if (t < TG_KBD) {   // K'_ad += sum_bc v D_bc
+                        const int ia = (t - TG_KAD) / ND, id = (t - TG_KAD) % ND;
+                        for (int ib = 0; ib < NB; ++ib)
+                            for (int ic = 0; ic < NC; ++ic)
+                                sum += blk[(ia * NB + ib) * NCD + ic * ND + id] * den[DO_BC + ib * NC + ic];
+                        atomicAdd(&Kh[(size_t)(f1 + ia) * N + f4 + id], sum);
+                    } else {   // K'_bd += sum_ac v D_ac
+                        const int ib = (t - TG_KBD) / ND, id = (t - TG_KBD) % ND;
+                        for (int ia = 0; ia < NA; ++ia)
+                            for (int ic = 0; ic < NC; ++ic)
+                                sum += blk[(ia * NB + ib) * NCD + ic * ND + id] * den[DO_AC + ia * NC + ic];
+                        atomicAdd(&Kh[(size_t)(f2 + ib) * N + f4 + id], sum);
                     }
                 }
+                __syncthreads();
             }
         }
     }
@@ -673,6 +778,9 @@ __host__ __device__ constexpr int variant_budget(int v) {
     return v == 0 ? 96 : (v == 1 ? 128 : (v == 2 ? 160 : 0));
 }
 constexpr int MAX_CHUNKS = 24;
+
+// LDS per wave for the staged bra primitives of the lane kernel
+constexpr int STAGE_BYTES = 3072;
 
 template <int LA, int LB, int LC, int LD, int BUDGET>
 __host__ __device__ constexpr bool lane_fits() {
@@ -695,8 +803,14 @@ void launch_budget(int ntile, int wpb, const EriArgs &a, hipStream_t s) {
         constexpr int CA = chunk_a(LA, LB, LC, LD, BUDGET), CDC = chunk_cd(LA, LB, LC, LD, BUDGET);
         int blocks = (ntile + wpb - 1) / wpb;
         if (blocks > 8192) blocks = 8192;
+        // LDS stage of the bra primitives: up to STAGE_BYTES per wave
+        constexpr int per_prim = 4 * (int)sizeof(double) + n_entries(LA, LB) * (int)sizeof(T);
+        EriArgs b = a;
+        b.stage_prims = STAGE_BYTES / per_prim < 1 ? 1 : STAGE_BYTES / per_prim;
+        if (b.stage_prims > a.bra.kmax) b.stage_prims = a.bra.kmax > 0 ? a.bra.kmax : 1;
+        b.stage_bytes = LA == 2 ? (b.stage_prims * per_prim + 15) / 16 * 16 : 0;
         hipLaunchKernelGGL((k_eri_lane<LA, LB, LC, LD, T, STORE, CA, CDC>), dim3(blocks),
-                           dim3(64 * wpb), 0, s, a);
+                           dim3(64 * wpb), (size_t)wpb * b.stage_bytes, s, b);
     } else {
         launch_wave_kernel<LA, LB, LC, LD, T, STORE>(ntile, a, s);
     }

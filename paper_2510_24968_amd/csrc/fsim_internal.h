@@ -150,6 +150,9 @@ struct EriArgs {
     // > 0: Jh and Kh each hold one copy per XCD, xcd_stride elements apart,
     // and a wave adds into the copy of the XCD it runs on (0: one copy)
     long long xcd_stride;
+    // lane kernels: each wave stages up to stage_prims primitive pairs of its
+    // bra (p, P, Hermite boxes) in stage_bytes of dynamic LDS
+    int stage_prims, stage_bytes;
     int nbf;
     const long long *mol_off;   // [nmol] offset of each molecule's N_m x N_m block
     const int *mol_n;           // [nmol] N_m

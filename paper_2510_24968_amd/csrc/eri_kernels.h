@@ -152,6 +152,126 @@ __host__ __device__ constexpr int n_chunks(int la, int lb, int lc, int ld, int l
     return ((ncart(la) + ca - 1) / ca) * ((ncart(lc) * ncart(ld) + cdc - 1) / cdc);
 }
 
+// Digest of one chunk of a lane's block (components a in [A0, A1), ket
+// component pairs in [CD0, CD1)) into the half-sums of Eq. fock:
+// J'_ab += 2 v D_cd (wave-reduced), J'_cd += 2 v D_ab, K'_ac += v D_bd,
+// K'_bc += v D_ad, K'_ad += v D_bc, K'_bd += v D_ac (fac: degeneracy factor,
+// 0 for an idle lane).
+template <int LA, int LB, int LC, int LD, typename T, int A0, int A1, int CD0, int CD1>
+__device__ __forceinline__ void digest_chunk(const T (&out)[(A1 - A0) * ncart(LB)][CD1 - CD0],
+                                             const double *__restrict__ D, double *__restrict__ Jh,
+                                             double *__restrict__ Kh, int N, int f1, int f2, int f3,
+                                             int f4, double fac, bool active) {
+    constexpr int NB = ncart(LB), NC = ncart(LC), ND = ncart(LD);
+    constexpr int NAc = A1 - A0, NABc = NAc * NB, NCDc = CD1 - CD0;
+    const int lane = threadIdx.x & 63;
+    // J'_ab (partial over this chunk's cd): pre-reduced over the wave
+    static_for<NABc>([&](auto abl_) {
+        constexpr int abl = decltype(abl_)::value;
+        constexpr int ia = A0 + abl / NB, ib = abl % NB;
+        double sum = 0.0;
+        static_for<NCDc>([&](auto cdl_) {
+            constexpr int cdl = decltype(cdl_)::value;
+            constexpr int ic = (CD0 + cdl) / ND, id = (CD0 + cdl) % ND;
+            sum += (double)out[abl][cdl] * D[(size_t)(f3 + ic) * N + f4 + id];
+        });
+        sum = wave_sum(2.0 * fac * sum);
+        if (lane == 0) atomicAdd(&Jh[(size_t)(f1 + ia) * N + f2 + ib], sum);
+    });
+    if (active) {
+        // J'_cd (partial over this chunk's a)
+        static_for<NCDc>([&](auto cdl_) {
+            constexpr int cdl = decltype(cdl_)::value;
+            constexpr int ic = (CD0 + cdl) / ND, id = (CD0 + cdl) % ND;
+            double sum = 0.0;
+            static_for<NABc>([&](auto abl_) {
+                constexpr int abl = decltype(abl_)::value;
+                constexpr int ia = A0 + abl / NB, ib = abl % NB;
+                sum += (double)out[abl][cdl] * D[(size_t)(f1 + ia) * N + f2 + ib];
+            });
+            atomicAdd(&Jh[(size_t)(f3 + ic) * N + f4 + id], 2.0 * fac * sum);
+        });
+        // K'_xc for x in {a (with D_bd), b (with D_ad)} and every c in the chunk
+        static_for<NC>([&](auto c_) {
+            constexpr int ic = decltype(c_)::value;
+            constexpr bool has_c = ic * ND + ND > CD0 && ic * ND < CD1;
+            if constexpr (has_c) {
+                static_for<NAc>([&](auto al_) {
+                    constexpr int al = decltype(al_)::value;
+                    double sum = 0.0;
+                    static_for<NB>([&](auto b_) {
+                        constexpr int ib = decltype(b_)::value;
+                        static_for<ND>([&](auto d_) {
+                            constexpr int id = decltype(d_)::value;
+                            constexpr int cd = ic * ND + id;
+                            if constexpr (cd >= CD0 && cd < CD1)
+                                sum += (double)out[al * NB + ib][cd - CD0] *
+                                       D[(size_t)(f2 + ib) * N + f4 + id];
+                        });
+                    });
+                    atomicAdd(&Kh[(size_t)(f1 + A0 + al) * N + f3 + ic], fac * sum);
+                });
+                static_for<NB>([&](auto b_) {
+                    constexpr int ib = decltype(b_)::value;
+                    double sum = 0.0;
+                    static_for<NAc>([&](auto al_) {
+                        constexpr int al = decltype(al_)::value;
+                        static_for<ND>([&](auto d_) {
+                            constexpr int id = decltype(d_)::value;
+                            constexpr int cd = ic * ND + id;
+                            if constexpr (cd >= CD0 && cd < CD1)
+                                sum += (double)out[al * NB + ib][cd - CD0] *
+                                       D[(size_t)(f1 + A0 + al) * N + f4 + id];
+                        });
+                    });
+                    atomicAdd(&Kh[(size_t)(f2 + ib) * N + f3 + ic], fac * sum);
+                });
+            }
+        });
+        // K'_xd for x in {a (with D_bc), b (with D_ac)} and every d in the chunk
+        static_for<ND>([&](auto d_) {
+            constexpr int id = decltype(d_)::value;
+            constexpr bool has_d = [] {
+                for (int c = 0; c < NC; ++c)
+                    if (c * ND + id >= CD0 && c * ND + id < CD1) return true;
+                return false;
+            }();
+            if constexpr (has_d) {
+                static_for<NAc>([&](auto al_) {
+                    constexpr int al = decltype(al_)::value;
+                    double sum = 0.0;
+                    static_for<NB>([&](auto b_) {
+                        constexpr int ib = decltype(b_)::value;
+                        static_for<NC>([&](auto c_) {
+                            constexpr int ic = decltype(c_)::value;
+                            constexpr int cd = ic * ND + id;
+                            if constexpr (cd >= CD0 && cd < CD1)
+                                sum += (double)out[al * NB + ib][cd - CD0] *
+                                       D[(size_t)(f2 + ib) * N + f3 + ic];
+                        });
+                    });
+                    atomicAdd(&Kh[(size_t)(f1 + A0 + al) * N + f4 + id], fac * sum);
+                });
+                static_for<NB>([&](auto b_) {
+                    constexpr int ib = decltype(b_)::value;
+                    double sum = 0.0;
+                    static_for<NAc>([&](auto al_) {
+                        constexpr int al = decltype(al_)::value;
+                        static_for<NC>([&](auto c_) {
+                            constexpr int ic = decltype(c_)::value;
+                            constexpr int cd = ic * ND + id;
+                            if constexpr (cd >= CD0 && cd < CD1)
+                                sum += (double)out[al * NB + ib][cd - CD0] *
+                                       D[(size_t)(f1 + A0 + al) * N + f3 + ic];
+                        });
+                    });
+                    atomicAdd(&Kh[(size_t)(f2 + ib) * N + f4 + id], fac * sum);
+                });
+            }
+        });
+    }
+}
+
 // Minimum waves per SIMD the lane kernel is compiled for.  d bras with a
 // live set of up to 128 FP64 values are held to two resident waves (256
 // registers each); every other kernel is left to the compiler, which
@@ -378,112 +498,181 @@ __global__ __launch_bounds__(256, lane_min_waves(LA, LB, LC, LD, CA, CDC)) void 
                     });
                 }
             } else {
-                // J'_ab (partial over this chunk's cd): pre-reduced over the wave
-                static_for<NABc>([&](auto abl_) {
-                    constexpr int abl = decltype(abl_)::value;
-                    constexpr int ia = A0 + abl / NB, ib = abl % NB;
-                    double sum = 0.0;
+                digest_chunk<LA, LB, LC, LD, T, A0, A1, CD0, CD1>(out, D, Jh, Kh, N, f1, f2, f3, f4,
+                                                                  fac, active);
+            }
+        });
+    }
+}
+
+// ===========================================================================
+// Kernel A, ket-outer order (ss, ps, pp and ds bras, Fock mode).  The same lane-per-
+// quartet tiles as k_eri_lane, with the primitive loops swapped: each ket
+// primitive's data are loaded once and held in registers while the bra
+// primitives (staged in LDS for the whole wave) run inside, and the bra
+// contraction is applied per primitive quartet:
+//   V_{tuv,cd} = sum_{tau nu phi} (-1)^{tau+nu+phi} E^{cd}_{tau nu phi} R^0_{t+tau,u+nu,v+phi}
+//   (ab|cd)   += sum_tuv E^{ab}_{tuv} V_{tuv,cd}
+// This trades the once-per-bra-primitive bra step for one per primitive
+// quartet (cheap for small bra boxes) against loading every ket primitive
+// once per quartet instead of once per bra primitive.
+// ===========================================================================
+template <int LA, int LB, int LC, int LD, typename T, int CA, int CDC>
+__global__ __launch_bounds__(256) void k_eri_lane_ko(EriArgs a) {
+    constexpr int L = LA + LB + LC + LD, LAB = LA + LB;
+    constexpr int NA = ncart(LA), NB = ncart(LB), NC = ncart(LC), ND = ncart(LD);
+    constexpr int NCD = NC * ND, NHAB = nherm(LAB), NH = nherm(L);
+    constexpr int NEB = n_entries(LA, LB), NEK = n_entries(LC, LD);
+    constexpr int NCHA = (NA + CA - 1) / CA, NCHCD = (NCD + CDC - 1) / CDC;
+    __shared__ double tab[BOYS_LDS];
+    extern __shared__ __align__(16) unsigned char stage_lds[];
+    boys_stage(tab, a.boys, L);
+    __syncthreads();
+    const int lane = threadIdx.x & 63;
+    const int wpb = blockDim.x >> 6;
+    const int ntile = a.tl.ntile;
+    const T *__restrict__ Eb = etab<T>(a.bra);
+    const T *__restrict__ Ek = etab<T>(a.ket);
+    const size_t nb = a.bra.n, nk = a.ket.n;
+    const long long xoff = a.xcd_stride ? xcd_index() * a.xcd_stride : 0;
+    // every bra primitive of the tile is staged (the launch checks kmax fits)
+    double *__restrict__ sp = (double *)(stage_lds + (size_t)(threadIdx.x >> 6) * a.stage_bytes);
+    T *__restrict__ se = (T *)(sp + 4 * a.stage_prims);
+
+    for (int tile0 = blockIdx.x * wpb + (threadIdx.x >> 6); tile0 < ntile;
+         tile0 += gridDim.x * wpb) {
+        const int tile = __builtin_amdgcn_readfirstlane(tile0);
+        const int b = tile_bra(a.tl, tile);
+        const int bra = __builtin_amdgcn_readfirstlane(a.tl.bra[b]);
+        const int k0 = a.tl.ket_lo[b] + (tile - a.tl.tile_start[b]) * TILE;
+        int ket = k0 + lane;
+        const bool active = ket < a.tl.ket_hi[b];
+        if (!active) ket = k0;
+        const int nbp = __builtin_amdgcn_readfirstlane(a.bra.nprim[bra]);
+        const int nkp = active ? a.ket.nprim[ket] : 0;
+        const int mol = __builtin_amdgcn_readfirstlane(a.bra.mol[bra]);
+        const long long mbase = a.mol_off[mol];
+        const int N = a.mol_n[mol];
+        const double *__restrict__ D = a.D + mbase;
+        double *__restrict__ Jh = a.Jh + xoff + mbase;
+        double *__restrict__ Kh = a.Kh + xoff + mbase;
+        const int f1 = __builtin_amdgcn_readfirstlane(a.bra.bf1[bra]);
+        const int f2 = __builtin_amdgcn_readfirstlane(a.bra.bf2[bra]);
+        const int f3 = a.ket.bf1[ket], f4 = a.ket.bf2[ket];
+        double fac = active ? 1.0 : 0.0;
+        if (a.bra.sh1[bra] == a.bra.sh2[bra]) fac *= 0.5;
+        if (a.ket.sh1[ket] == a.ket.sh2[ket]) fac *= 0.5;
+        if (a.same_class && ket == bra) fac *= 0.5;
+
+        // stage the bra primitives: p, P (4 doubles) and the Hermite boxes
+        for (int x = lane; x < nbp * 4; x += 64) {
+            const int s = x >> 2, f = x & 3;
+            sp[x] = f == 0 ? a.bra.p[(size_t)s * nb + bra] : a.bra.P[((size_t)s * 3 + f - 1) * nb + bra];
+        }
+        for (int x = lane; x < nbp * NEB; x += 64) se[x] = Eb[(size_t)x * nb + bra];
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+
+        static_for<NCHA * NCHCD>([&](auto ch_) {
+            constexpr int ch = decltype(ch_)::value;
+            constexpr int A0 = (ch / NCHCD) * CA, A1 = cmin(A0 + CA, NA);
+            constexpr int CD0 = (ch % NCHCD) * CDC, CD1 = cmin(CD0 + CDC, NCD);
+            constexpr int NAc = A1 - A0, NABc = NAc * NB, NCDc = CD1 - CD0;
+            constexpr int EK0 = box_off(LC, LD, CD0);
+            constexpr int EK1 = CD1 < NCD ? box_off(LC, LD, CD1) : NEK;
+            T out[NABc][NCDc];
+#pragma unroll
+            for (int x = 0; x < NABc; ++x)
+#pragma unroll
+                for (int y = 0; y < NCDc; ++y) out[x][y] = T(0);
+
+            for (int j = 0; j < nkp; ++j) {
+                // this ket primitive, held across the bra primitives
+                const double q = a.ket.p[(size_t)j * nk + ket];
+                const double Kx = a.ket.P[((size_t)j * 3 + 0) * nk + ket];
+                const double Ky = a.ket.P[((size_t)j * 3 + 1) * nk + ket];
+                const double Kz = a.ket.P[((size_t)j * 3 + 2) * nk + ket];
+                T ek[EK1 - EK0];
+                const T *__restrict__ ekp = Ek + (size_t)j * NEK * nk + ket;
+#pragma unroll
+                for (int e = EK0; e < EK1; ++e) {
+                    T ev = ekp[(size_t)e * nk];
+                    ek[e - EK0] = ev;
+                }
+                for (int i = 0; i < nbp; ++i) {
+                    const double p = sp[i * 4 + 0];
+                    const double X = sp[i * 4 + 1] - Kx, Y = sp[i * 4 + 2] - Ky,
+                                 Z = sp[i * 4 + 3] - Kz;
+                    const double rs = rsqrt(p + q);
+                    const double alpha = p * q * (rs * rs);
+                    double F[L + 1];
+                    boys_eval<L>(alpha * (X * X + Y * Y + Z * Z), tab, F);
+                    T src[L + 1];
+                    double m = rs;
+#pragma unroll
+                    for (int n = 0; n <= L; ++n) {
+                        src[n] = T(F[n] * m);
+                        m *= -2.0 * alpha;
+                    }
+                    T r[NH];
+                    hermite_r<L, T>(src, T(X), T(Y), T(Z), r);
+                    // ket step for this primitive quartet
+                    T V[NCDc][NHAB];
                     static_for<NCDc>([&](auto cdl_) {
                         constexpr int cdl = decltype(cdl_)::value;
-                        constexpr int ic = (CD0 + cdl) / ND, id = (CD0 + cdl) % ND;
-                        sum += (double)out[abl][cdl] * D[(size_t)(f3 + ic) * N + f4 + id];
-                    });
-                    sum = wave_sum(2.0 * fac * sum);
-                    if (lane == 0) atomicAdd(&Jh[(size_t)(f1 + ia) * N + f2 + ib], sum);
-                });
-                if (active) {
-                    // J'_cd (partial over this chunk's a)
-                    static_for<NCDc>([&](auto cdl_) {
-                        constexpr int cdl = decltype(cdl_)::value;
-                        constexpr int ic = (CD0 + cdl) / ND, id = (CD0 + cdl) % ND;
-                        double sum = 0.0;
-                        static_for<NABc>([&](auto abl_) {
-                            constexpr int abl = decltype(abl_)::value;
-                            constexpr int ia = A0 + abl / NB, ib = abl % NB;
-                            sum += (double)out[abl][cdl] * D[(size_t)(f1 + ia) * N + f2 + ib];
+                        constexpr int cd = CD0 + cdl;
+                        constexpr int bx = box_dim(LC, LD, cd, 0), by = box_dim(LC, LD, cd, 1),
+                                      bz = box_dim(LC, LD, cd, 2);
+                        constexpr int eo = box_off(LC, LD, cd);
+                        static_for<NHAB>([&](auto h_) { V[cdl][decltype(h_)::value] = T(0); });
+                        static_for<bx + 1>([&](auto ta_) {
+                            constexpr int ta = decltype(ta_)::value;
+                            static_for<by + 1>([&](auto nu_) {
+                                constexpr int nu = decltype(nu_)::value;
+                                static_for<bz + 1>([&](auto ph_) {
+                                    constexpr int ph = decltype(ph_)::value;
+                                    constexpr int e = eo + (ta * (by + 1) + nu) * (bz + 1) + ph;
+                                    T ev = ek[e - EK0];
+                                    if constexpr ((ta + nu + ph) & 1) ev = -ev;
+                                    static_for<NHAB>([&](auto h_) {
+                                        constexpr int h = decltype(h_)::value;
+                                        constexpr int ri = hidx(hidx_t(h) + ta, hidx_u(h) + nu,
+                                                                hidx_v(h) + ph);
+                                        V[cdl][h] = fma(ev, r[ri], V[cdl][h]);
+                                    });
+                                });
+                            });
                         });
-                        atomicAdd(&Jh[(size_t)(f3 + ic) * N + f4 + id], 2.0 * fac * sum);
                     });
-                    // K'_xc for x in {a (with D_bd), b (with D_ad)} and every c in the chunk
-                    static_for<NC>([&](auto c_) {
-                        constexpr int ic = decltype(c_)::value;
-                        constexpr bool has_c = ic * ND + ND > CD0 && ic * ND < CD1;
-                        if constexpr (has_c) {
-                            static_for<NAc>([&](auto al_) {
-                                constexpr int al = decltype(al_)::value;
-                                double sum = 0.0;
-                                static_for<NB>([&](auto b_) {
-                                    constexpr int ib = decltype(b_)::value;
-                                    static_for<ND>([&](auto d_) {
-                                        constexpr int id = decltype(d_)::value;
-                                        constexpr int cd = ic * ND + id;
-                                        if constexpr (cd >= CD0 && cd < CD1)
-                                            sum += (double)out[al * NB + ib][cd - CD0] *
-                                                   D[(size_t)(f2 + ib) * N + f4 + id];
+                    // bra step for this primitive quartet (boxes from LDS)
+                    const T *__restrict__ eb = se + i * NEB;
+                    static_for<NABc>([&](auto abl_) {
+                        constexpr int abl = decltype(abl_)::value;
+                        constexpr int ab = (A0 + abl / NB) * NB + abl % NB;
+                        constexpr int ax = box_dim(LA, LB, ab, 0), ay = box_dim(LA, LB, ab, 1),
+                                      az = box_dim(LA, LB, ab, 2);
+                        constexpr int ao = box_off(LA, LB, ab);
+                        static_for<ax + 1>([&](auto t_) {
+                            constexpr int t = decltype(t_)::value;
+                            static_for<ay + 1>([&](auto u_) {
+                                constexpr int u = decltype(u_)::value;
+                                static_for<az + 1>([&](auto v_) {
+                                    constexpr int v = decltype(v_)::value;
+                                    constexpr int e = ao + (t * (ay + 1) + u) * (az + 1) + v;
+                                    const T ebv = eb[e];
+                                    static_for<NCDc>([&](auto cdl_) {
+                                        constexpr int cdl = decltype(cdl_)::value;
+                                        out[abl][cdl] = fma(ebv, V[cdl][hidx(t, u, v)], out[abl][cdl]);
                                     });
                                 });
-                                atomicAdd(&Kh[(size_t)(f1 + A0 + al) * N + f3 + ic], fac * sum);
                             });
-                            static_for<NB>([&](auto b_) {
-                                constexpr int ib = decltype(b_)::value;
-                                double sum = 0.0;
-                                static_for<NAc>([&](auto al_) {
-                                    constexpr int al = decltype(al_)::value;
-                                    static_for<ND>([&](auto d_) {
-                                        constexpr int id = decltype(d_)::value;
-                                        constexpr int cd = ic * ND + id;
-                                        if constexpr (cd >= CD0 && cd < CD1)
-                                            sum += (double)out[al * NB + ib][cd - CD0] *
-                                                   D[(size_t)(f1 + A0 + al) * N + f4 + id];
-                                    });
-                                });
-                                atomicAdd(&Kh[(size_t)(f2 + ib) * N + f3 + ic], fac * sum);
-                            });
-                        }
-                    });
-                    // K'_xd for x in {a (with D_bc), b (with D_ac)} and every d in the chunk
-                    static_for<ND>([&](auto d_) {
-                        constexpr int id = decltype(d_)::value;
-                        constexpr bool has_d = [] {
-                            for (int c = 0; c < NC; ++c)
-                                if (c * ND + id >= CD0 && c * ND + id < CD1) return true;
-                            return false;
-                        }();
-                        if constexpr (has_d) {
-                            static_for<NAc>([&](auto al_) {
-                                constexpr int al = decltype(al_)::value;
-                                double sum = 0.0;
-                                static_for<NB>([&](auto b_) {
-                                    constexpr int ib = decltype(b_)::value;
-                                    static_for<NC>([&](auto c_) {
-                                        constexpr int ic = decltype(c_)::value;
-                                        constexpr int cd = ic * ND + id;
-                                        if constexpr (cd >= CD0 && cd < CD1)
-                                            sum += (double)out[al * NB + ib][cd - CD0] *
-                                                   D[(size_t)(f2 + ib) * N + f3 + ic];
-                                    });
-                                });
-                                atomicAdd(&Kh[(size_t)(f1 + A0 + al) * N + f4 + id], fac * sum);
-                            });
-                            static_for<NB>([&](auto b_) {
-                                constexpr int ib = decltype(b_)::value;
-                                double sum = 0.0;
-                                static_for<NAc>([&](auto al_) {
-                                    constexpr int al = decltype(al_)::value;
-                                    static_for<NC>([&](auto c_) {
-                                        constexpr int ic = decltype(c_)::value;
-                                        constexpr int cd = ic * ND + id;
-                                        if constexpr (cd >= CD0 && cd < CD1)
-                                            sum += (double)out[al * NB + ib][cd - CD0] *
-                                                   D[(size_t)(f1 + A0 + al) * N + f3 + ic];
-                                    });
-                                });
-                                atomicAdd(&Kh[(size_t)(f2 + ib) * N + f4 + id], fac * sum);
-                            });
-                        }
+                        });
                     });
                 }
             }
+            digest_chunk<LA, LB, LC, LD, T, A0, A1, CD0, CD1>(out, D, Jh, Kh, N, f1, f2, f3, f4, fac,
+                                                              active);
         });
     }
 }
@@ -766,21 +955,29 @@ __global__ __launch_bounds__(64) void k_eri_wave(EriArgs a) {
     }
 }
 
-// Launch variants.  A variant fixes the per-lane register budget of kernel A
-// (live block + W + R^0 values; the chunking follows from it); the last one
-// is kernel B.  A budget whose chunking does not fit, or needs more than
-// MAX_CHUNKS chunks, also falls back to kernel B.  The autotuner picks a
-// variant and the waves per block for every class and precision.
-constexpr int NVARIANT = 4;
-constexpr int VARIANT_WAVE = NVARIANT - 1;
+// Launch variants.  Variants 0..2 fix the per-lane register budget of kernel
+// A (live block + W + R^0 values; the chunking follows from it); variant 3 is
+// kernel B; variant 4 is kernel A in ket-outer order (bras with small
+// Hermite boxes: ss, ps, pp, ds; other classes run the default variant).  A budget whose chunking does not
+// fit, or needs more than MAX_CHUNKS chunks, falls back to kernel B.  The
+// autotuner picks a variant and the waves per block for every class and
+// precision.
+constexpr int NVARIANT = 5;
+constexpr int VARIANT_WAVE = 3;
+constexpr int VARIANT_KO = 4;
 constexpr int DEFAULT_VARIANT = 1;
 __host__ __device__ constexpr int variant_budget(int v) {
     return v == 0 ? 96 : (v == 1 ? 128 : (v == 2 ? 160 : 0));
 }
 constexpr int MAX_CHUNKS = 24;
 
-// LDS per wave for the staged bra primitives of the lane kernel
+// LDS per wave for the staged bra primitives of the lane kernel, and the
+// most the ket-outer kernel may stage (all primitives of the bra)
 constexpr int STAGE_BYTES = 3072;
+constexpr int KO_STAGE_MAX = 8192;
+// the ket-outer kernel serves bra classes with small Hermite boxes (ss, ps,
+// pp, ds: 1, 6, 33, 21 entries), whose per-quartet bra step is cheap
+constexpr int KO_MAX_BRA_BOX = 33;
 
 template <int LA, int LB, int LC, int LD, int BUDGET>
 __host__ __device__ constexpr bool lane_fits() {
@@ -817,6 +1014,27 @@ void launch_budget(int ntile, int wpb, const EriArgs &a, hipStream_t s) {
 }
 
 template <int LA, int LB, int LC, int LD, typename T>
+void launch_ko(int ntile, int wpb, const EriArgs &a, hipStream_t s) {
+    constexpr int BUDGET = variant_budget(DEFAULT_VARIANT);
+    if constexpr (n_entries(LA, LB) <= KO_MAX_BRA_BOX && lane_fits<LA, LB, LC, LD, BUDGET>()) {
+        constexpr int CA = chunk_a(LA, LB, LC, LD, BUDGET), CDC = chunk_cd(LA, LB, LC, LD, BUDGET);
+        constexpr int per_prim = 4 * (int)sizeof(double) + n_entries(LA, LB) * (int)sizeof(T);
+        const int kmax = a.bra.kmax > 0 ? a.bra.kmax : 1;
+        if (kmax * per_prim <= KO_STAGE_MAX) {
+            EriArgs b = a;
+            b.stage_prims = kmax;
+            b.stage_bytes = (kmax * per_prim + 15) / 16 * 16;
+            int blocks = (ntile + wpb - 1) / wpb;
+            if (blocks > 8192) blocks = 8192;
+            hipLaunchKernelGGL((k_eri_lane_ko<LA, LB, LC, LD, T, CA, CDC>), dim3(blocks),
+                               dim3(64 * wpb), (size_t)wpb * b.stage_bytes, s, b);
+            return;
+        }
+    }
+    launch_budget<LA, LB, LC, LD, T, false, BUDGET>(ntile, wpb, a, s);
+}
+
+template <int LA, int LB, int LC, int LD, typename T>
 hipError_t launch_class(bool store, int variant, int wpb, const EriArgs &a, hipStream_t s) {
     const int ntile = store ? a.st_ntile : a.tl.ntile;
     if (ntile <= 0) return hipSuccess;
@@ -830,6 +1048,7 @@ hipError_t launch_class(bool store, int variant, int wpb, const EriArgs &a, hipS
         case 0: launch_budget<LA, LB, LC, LD, T, false, variant_budget(0)>(ntile, wpb, a, s); break;
         case 1: launch_budget<LA, LB, LC, LD, T, false, variant_budget(1)>(ntile, wpb, a, s); break;
         case 2: launch_budget<LA, LB, LC, LD, T, false, variant_budget(2)>(ntile, wpb, a, s); break;
+        case VARIANT_KO: launch_ko<LA, LB, LC, LD, T>(ntile, wpb, a, s); break;
         default: launch_wave_kernel<LA, LB, LC, LD, T, false>(ntile, a, s); break;
     }
     return hipGetLastError();

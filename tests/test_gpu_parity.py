@@ -333,11 +333,12 @@ def test_many_contexts_in_a_row():
     assert worst < 1e-12
 
 
-@pytest.mark.parametrize("variant", [0, 1, 2, 3])
+@pytest.mark.parametrize("variant", [0, 1, 2, 3, 4])
 def test_every_kernel_variant_matches_oracle(variant):
     """Each launch variant the autotuner may pick (three register budgets of
-    the lane kernel, the wave kernel) and each waves-per-block setting gives
-    the oracle's J and K for every quartet class."""
+    the lane kernel, the wave kernel, the ket-outer lane kernel) and each
+    waves-per-block setting gives the oracle's J and K for every quartet
+    class."""
     b = spd_molecule()
     ctx = _ctx(b)
     ctx.schwarz_screen(tau=0.0)
@@ -351,6 +352,24 @@ def test_every_kernel_variant_matches_oracle(variant):
             assert np.max(np.abs(r["K"].cpu().numpy() - Ko)) < tol, (variant, wpb, prec)
 
 
+@pytest.mark.parametrize("wpb", [1, 4])
+def test_ket_outer_kernel_water_mixed(wpb):
+    """The ket-outer lane kernel on three-primitive s/p shells, in FP64 and
+    with FP32 tiles, against the oracle."""
+    b = synth.water_cluster(2, 8)
+    ctx = _ctx(b, tau=1e-12, tau_fp32=1e-6)
+    ctx.schwarz_screen()
+    ctx.set_all_variants(4, wpb)
+    D = _random_density(ctx.nbf, 12) * 0.1
+    Jo, Ko = oracle.Basis(b).fock_jk(D, tau=1e-12)
+    r = ctx.fock_build(_dev(D), precision="fp64", want_jk=True)
+    assert np.max(np.abs(r["J"].cpu().numpy() - Jo)) < 1e-11
+    assert np.max(np.abs(r["K"].cpu().numpy() - Ko)) < 1e-11
+    rm = ctx.fock_build(_dev(D), precision="mixed", want_jk=True)
+    assert np.max(np.abs(rm["J"].cpu().numpy() - Jo)) < 1e-6
+    assert np.max(np.abs(rm["K"].cpu().numpy() - Ko)) < 1e-6
+
+
 def test_autotune_then_parity():
     from paper_2510_24968_amd import autotune
     b = synth.water_cluster(3, 4)
@@ -360,7 +379,7 @@ def test_autotune_then_parity():
     D0 = ctx.core_guess()
     table = autotune.tune(ctx, D0)
     assert len(table) > 0
-    assert all(0 <= r["variant"] < 4 and r["waves_per_block"] in (1, 2, 4) for r in table.values())
+    assert all(0 <= r["variant"] < 5 and r["waves_per_block"] in (1, 2, 4) for r in table.values())
     D = D0.cpu().numpy()
     Jo, Ko = oracle.Basis(b).fock_jk(D, tau=tau)
     r = ctx.fock_build(D0, want_jk=True)

@@ -51,8 +51,8 @@ def _per_dispatch(path):
 
 
 def _class_of(name):
-    m = re.search(r"k_eri_(?:lane|wave)<(\d), (\d), (\d), (\d), (double|float), false", name)
-    if not m:
+    m = re.search(r"k_eri_(?:lane_ko|lane|wave)<(\d), (\d), (\d), (\d), (double|float)(, true)?", name)
+    if not m or m.group(6):      # stored-block (screening) launches are not Fock-build work
         return None
     la, lb, lc, ld = (int(m.group(i)) for i in range(1, 5))
     return f"({PAIR[(la, lb)]}|{PAIR[(lc, ld)]})" + ("" if m.group(5) == "double" else " f32")

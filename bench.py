@@ -111,6 +111,14 @@ def run_batch(a, basis_list, w):
     t0 = time.time()
     _, st = bt.schwarz_screen()
     t_screen = time.time() - t0
+    from paper_2510_24968_amd import autotune
+    tuning_src = None
+    path = a.tuning or os.path.join(ROOT, "paper_2510_24968_amd", "tuning",
+                                    f"{a.workload}_mi355x.json")
+    if os.path.exists(path):
+        n = autotune.apply(bt, autotune.load(path))
+        tuning_src = f"{os.path.relpath(path, ROOT)} ({n} class settings)"
+    log(f"tuning: {tuning_src or 'library defaults'}")
     bt.set_graph(True)
     log(f"{len(basis_list)} molecules, N_m {bt.nbf_mol.min()}..{bt.nbf_mol.max()}, "
         f"{st['quartets_kept']} quartets kept; setup {t_setup:.2f}s screen {t_screen:.2f}s")
@@ -169,7 +177,8 @@ def run_batch(a, basis_list, w):
                                f"2-24 atoms, N_m {int(bt.nbf_mol.min())}-{int(bt.nbf_mol.max())}, "
                                f"batched with graph-captured Fock builds",
                    "tau_screen": w["tau"], "tau_fp32": tau32, "quartets_screened": nq,
-                   "quartets_canonical": st["quartets_total"], "parallelism": "single GPU"},
+                   "quartets_canonical": st["quartets_total"], "parallelism": "single GPU",
+                   "tuning": tuning_src or "library defaults"},
         "fp64": out["fp64"],
         "mixed": dict(out["mixed"], value=nq * 1e3 / out["mixed"]["ms_per_step"],
                       dE_vs_fp64_max_Ha=float(dE.max()) if dE.size else None,

@@ -78,7 +78,10 @@ def main():
     import synth
     from paper_2510_24968_amd import fsim
     basis, w = synth.workload(a.workload)
-    ctx = fsim.Context(basis, tau=w["tau"], tau_fp32=w["tau_fp32"] or 1e-5)
+    if isinstance(basis, list):     # a batch of molecules in one context
+        ctx = fsim.Batch(basis, tau=w["tau"], tau_fp32=w["tau_fp32"] or 1e-5)
+    else:
+        ctx = fsim.Context(basis, tau=w["tau"], tau_fp32=w["tau_fp32"] or 1e-5)
     ctx.schwarz_screen()
     D = ctx.core_guess()
     t0 = time.time()

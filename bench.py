@@ -203,8 +203,8 @@ def main():
     ap.add_argument("--autotune", action="store_true", help="tune in-process before timing")
     a = ap.parse_args()
     if a.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
-              "(the sharding design is described in DESIGN.md); run with --gpus 1",
+        print("bench.py measures one GPU only: the Fock build has no multi-GPU path here; "
+              "run with --gpus 1",
               file=sys.stderr)
         sys.exit(2)
 

@@ -541,7 +541,7 @@ def main():
     ap.add_argument("--waters", type=int, default=512)
     ap.add_argument("--eval", type=int, default=16)
     ap.add_argument("--epochs", type=int, default=12)
-    ap.add_argument("--out", default="gpurun_out/guess")
+    ap.add_argument("--out", default="guess_out")
     a = ap.parse_args()
     os.makedirs(a.out, exist_ok=True)
     log = lambda s: print(f"[guess] {s}", flush=True)

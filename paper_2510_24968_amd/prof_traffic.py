@@ -8,7 +8,7 @@
         W/w64_counter_collection.csv --workload water64 --command "..."
 
 Both counters are in KiB per dispatch.  Each is scaled by what it reads for
-the driver's plain 1 GiB device copy (read 1 GiB, write 1 GiB), so the
+the counter run's plain 1 GiB device copy (read 1 GiB, write 1 GiB), so the
 result is bytes.  The summary records a digest of the kernel sources:
 readings from other sources do not describe the kernels any more.
 """

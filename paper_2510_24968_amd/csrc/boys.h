@@ -38,10 +38,6 @@ __device__ inline void boys_stage(double *lds, const double *__restrict__ g, int
 // F_0..F_L at T from a table staged for order L.
 template <int L>
 __device__ __forceinline__ void boys_eval(double T, const double *tab, double *F) {
-    // exp(-T) once, ahead of the branch: the lanes of a wave usually take
-    // both branches, which would otherwise evaluate it twice
-    double e = 0.0;
-    if constexpr (L > 0) e = exp(-T);
     if (T < BOYS_TMAX) {
         const int k = __double2int_rn(T * BOYS_INV_DT);
         const double d = k * BOYS_DT - T;
@@ -51,15 +47,14 @@ __device__ __forceinline__ void boys_eval(double T, const double *tab, double *F
         for (int j = BOYS_NTAYLOR - 2; j >= 0; --j) f = fma(f, d, c[j]);
         F[L] = f;
         if constexpr (L > 0) {
-            const double t2 = 2.0 * T;
+            const double e = exp(-T), t2 = 2.0 * T;
 #pragma unroll
             for (int n = L; n > 0; --n) F[n - 1] = fma(t2, F[n], e) * (1.0 / (2 * n - 1));
         }
     } else {
-        const double r = rsqrt(T);
-        F[0] = 0.88622692545275801365 * r;   // sqrt(pi)/2 / sqrt(T)
+        F[0] = 0.88622692545275801365 * rsqrt(T);   // sqrt(pi)/2 / sqrt(T)
         if constexpr (L > 0) {
-            const double h = 0.5 * r * r;    // 1 / (2T) without a division
+            const double e = exp(-T), h = 0.5 / T;
 #pragma unroll
             for (int n = 0; n < L; ++n) F[n + 1] = ((2 * n + 1) * F[n] - e) * h;
         }

@@ -61,6 +61,48 @@ __device__ __forceinline__ void boys_eval(double T, const double *tab, double *F
     }
 }
 
+// FP32 evaluation for the FP32 tiles (quartets whose Schwarz bound is below
+// the FP32 threshold): the same grid rounded to FP32 and 5 Taylor terms (the
+// truncation, at most 0.05^5/5! relative to F_L, is below FP32 rounding),
+// with the hardware single-precision exp and reciprocal square root.
+constexpr int BOYS_NTAYLOR32 = 5;
+constexpr int BOYS_LDS32 = BOYS_NT * BOYS_NTAYLOR32;
+
+__device__ inline void boys_stage32(float *lds, const double *__restrict__ g, int L) {
+    for (int i = threadIdx.x; i < BOYS_LDS32; i += blockDim.x) {
+        int k = i / BOYS_NTAYLOR32, j = i - k * BOYS_NTAYLOR32;
+        double s = 1.0;
+        for (int m = 2; m <= j; ++m) s *= m;
+        lds[i] = (float)(g[k * BOYS_NORD + L + j] / s);
+    }
+}
+
+template <int L>
+__device__ __forceinline__ void boys_eval32(float T, const float *tab, float *F) {
+    if (T < (float)BOYS_TMAX) {
+        const int k = __float2int_rn(T * (float)BOYS_INV_DT);
+        const float d = k * (float)BOYS_DT - T;
+        const float *c = tab + k * BOYS_NTAYLOR32;
+        float f = c[BOYS_NTAYLOR32 - 1];
+#pragma unroll
+        for (int j = BOYS_NTAYLOR32 - 2; j >= 0; --j) f = fmaf(f, d, c[j]);
+        F[L] = f;
+        if constexpr (L > 0) {
+            const float e = __expf(-T), t2 = 2.0f * T;
+#pragma unroll
+            for (int n = L; n > 0; --n) F[n - 1] = fmaf(t2, F[n], e) * (1.0f / (2 * n - 1));
+        }
+    } else {
+        const float r = rsqrtf(T);
+        F[0] = 0.886226925f * r;
+        if constexpr (L > 0) {
+            const float e = __expf(-T), h = 0.5f * r * r;
+#pragma unroll
+            for (int n = 0; n < L; ++n) F[n + 1] = ((2 * n + 1) * F[n] - e) * h;
+        }
+    }
+}
+
 // Runtime-L variant reading the full global grid (setup kernels only).
 __device__ inline void boys_eval_rt(int L, double T, const double *__restrict__ g, double *F) {
     if (T < BOYS_TMAX) {

@@ -23,6 +23,7 @@
 // every canonical quartet then count once).
 #pragma once
 
+#include <type_traits>
 #include <utility>
 
 #include "boys.h"
@@ -287,9 +288,12 @@ __global__ __launch_bounds__(256, lane_min_waves(LA, LB, LC, LD, CA, CDC)) void 
     constexpr int NCD = NC * ND, NHAB = nherm(LAB), NH = nherm(L);
     constexpr int NEB = n_entries(LA, LB), NEK = n_entries(LC, LD);
     constexpr int NCHA = (NA + CA - 1) / CA, NCHCD = (NCD + CDC - 1) / CDC;
-    __shared__ double tab[BOYS_LDS];
+    // Boys grid in LDS: FP64 for FP64 tiles, FP32 (5 terms) for FP32 tiles
+    constexpr bool F32 = std::is_same<T, float>::value;
+    __shared__ std::conditional_t<F32, float, double> tab[F32 ? BOYS_LDS32 : BOYS_LDS];
     extern __shared__ __align__(16) unsigned char stage_lds[];
-    boys_stage(tab, a.boys, L);
+    if constexpr (F32) boys_stage32(tab, a.boys, L);
+    else boys_stage(tab, a.boys, L);
     __syncthreads();
     const int lane = threadIdx.x & 63;
     const int wpb = blockDim.x >> 6;
@@ -417,16 +421,32 @@ __global__ __launch_bounds__(256, lane_min_waves(LA, LB, LC, LD, CA, CDC)) void 
                     const double X = Px - Kxn, Y = Py - Kyn, Z = Pz - Kzn;
                     if (STAGE && j + 1 < nkp) kload(j + 1);
                     // 1/sqrt(p+q) once; 1/(p+q) and alpha = pq/(p+q) from it
-                    const double rs = rsqrt(p + q);
-                    const double alpha = p * q * (rs * rs);
-                    double F[L + 1];
-                    boys_eval<L>(alpha * (X * X + Y * Y + Z * Z), tab, F);
                     T src[L + 1];
-                    double m = rs;
+                    if constexpr (F32) {
+                        // FP32 tile: prefactor, Boys and sources in FP32
+                        const float pf = (float)p, qf = (float)q;
+                        const float Xf = (float)X, Yf = (float)Y, Zf = (float)Z;
+                        const float rsf = rsqrtf(pf + qf);
+                        const float al = pf * qf * (rsf * rsf);
+                        float F[L + 1];
+                        boys_eval32<L>(al * (Xf * Xf + Yf * Yf + Zf * Zf), tab, F);
+                        float m = rsf;
 #pragma unroll
-                    for (int n = 0; n <= L; ++n) {
-                        src[n] = T(F[n] * m);
-                        m *= -2.0 * alpha;
+                        for (int n = 0; n <= L; ++n) {
+                            src[n] = F[n] * m;
+                            m *= -2.0f * al;
+                        }
+                    } else {
+                        const double rs = rsqrt(p + q);
+                        const double alpha = p * q * (rs * rs);
+                        double F[L + 1];
+                        boys_eval<L>(alpha * (X * X + Y * Y + Z * Z), tab, F);
+                        double m = rs;
+#pragma unroll
+                        for (int n = 0; n <= L; ++n) {
+                            src[n] = T(F[n] * m);
+                            m *= -2.0 * alpha;
+                        }
                     }
                     T r[NH];
                     hermite_r<L, T>(src, T(X), T(Y), T(Z), r);
@@ -524,9 +544,12 @@ __global__ __launch_bounds__(256) void k_eri_lane_ko(EriArgs a) {
     constexpr int NCD = NC * ND, NHAB = nherm(LAB), NH = nherm(L);
     constexpr int NEB = n_entries(LA, LB), NEK = n_entries(LC, LD);
     constexpr int NCHA = (NA + CA - 1) / CA, NCHCD = (NCD + CDC - 1) / CDC;
-    __shared__ double tab[BOYS_LDS];
+    // Boys grid in LDS: FP64 for FP64 tiles, FP32 (5 terms) for FP32 tiles
+    constexpr bool F32 = std::is_same<T, float>::value;
+    __shared__ std::conditional_t<F32, float, double> tab[F32 ? BOYS_LDS32 : BOYS_LDS];
     extern __shared__ __align__(16) unsigned char stage_lds[];
-    boys_stage(tab, a.boys, L);
+    if constexpr (F32) boys_stage32(tab, a.boys, L);
+    else boys_stage(tab, a.boys, L);
     __syncthreads();
     const int lane = threadIdx.x & 63;
     const int wpb = blockDim.x >> 6;
@@ -604,16 +627,32 @@ __global__ __launch_bounds__(256) void k_eri_lane_ko(EriArgs a) {
                     const double p = sp[i * 4 + 0];
                     const double X = sp[i * 4 + 1] - Kx, Y = sp[i * 4 + 2] - Ky,
                                  Z = sp[i * 4 + 3] - Kz;
-                    const double rs = rsqrt(p + q);
-                    const double alpha = p * q * (rs * rs);
-                    double F[L + 1];
-                    boys_eval<L>(alpha * (X * X + Y * Y + Z * Z), tab, F);
                     T src[L + 1];
-                    double m = rs;
+                    if constexpr (F32) {
+                        // FP32 tile: prefactor, Boys and sources in FP32
+                        const float pf = (float)p, qf = (float)q;
+                        const float Xf = (float)X, Yf = (float)Y, Zf = (float)Z;
+                        const float rsf = rsqrtf(pf + qf);
+                        const float al = pf * qf * (rsf * rsf);
+                        float F[L + 1];
+                        boys_eval32<L>(al * (Xf * Xf + Yf * Yf + Zf * Zf), tab, F);
+                        float m = rsf;
 #pragma unroll
-                    for (int n = 0; n <= L; ++n) {
-                        src[n] = T(F[n] * m);
-                        m *= -2.0 * alpha;
+                        for (int n = 0; n <= L; ++n) {
+                            src[n] = F[n] * m;
+                            m *= -2.0f * al;
+                        }
+                    } else {
+                        const double rs = rsqrt(p + q);
+                        const double alpha = p * q * (rs * rs);
+                        double F[L + 1];
+                        boys_eval<L>(alpha * (X * X + Y * Y + Z * Z), tab, F);
+                        double m = rs;
+#pragma unroll
+                        for (int n = 0; n <= L; ++n) {
+                            src[n] = T(F[n] * m);
+                            m *= -2.0 * alpha;
+                        }
                     }
                     T r[NH];
                     hermite_r<L, T>(src, T(X), T(Y), T(Z), r);

@@ -130,3 +130,20 @@ def test_ch_molecules_respect_their_construction():
         assert np.all((steps >= 2.0 - 1e-12) & (steps <= 2.9 + 1e-12))
         nbf = synth.nbf_of(b)
         assert nbf == sum(8 if t == "C" else 4 for t in b["types"])
+
+
+def test_product_path_fails_loudly_without_gpu_or_library(monkeypatch):
+    """No CPU fallback: without a GPU the context refuses to start, and
+    without the built library the binding raises instead of substituting
+    anything."""
+    import torch
+    from paper_2510_24968_amd import fsim
+    if not torch.cuda.is_available():
+        with pytest.raises(fsim.FsimError, match="GPU"):
+            fsim.Context(synth.h_chain(2, 1.4))
+        with pytest.raises(fsim.FsimError, match="GPU"):
+            fsim.Batch([synth.h_chain(2, 1.4)])
+    monkeypatch.setattr(fsim, "_lib", None)
+    monkeypatch.setattr(fsim, "LIBPATH", "/nonexistent/libfsim.so")
+    with pytest.raises(fsim.FsimError, match="not built"):
+        fsim.lib()

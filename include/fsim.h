@@ -203,7 +203,9 @@ fsim_status fsim_get_class_profile(fsim_ctx *ctx, fsim_class_profile *out, int32
  * a budget that cannot be met falls back to variant 3), variant 3 the
  * one-wave-per-quartet kernel, variant 4 the one-lane-per-quartet kernel with
  * the primitive loops in ket-outer order (ss, ps, pp and ds bra pairs; other
- * classes run variant 1).  waves_per_block is 1, 2 or 4. */
+ * classes run variant 1), variant 5 the one-lane-per-quartet kernel at a
+ * budget of 192 live values for classes whose chunks do not fit 160 (others
+ * run variant 2).  waves_per_block is 1, 2 or 4. */
 typedef struct {
     int32_t bra_class, ket_class;   /* pair classes, bra >= ket */
     int32_t fp32;

@@ -1200,7 +1200,7 @@ extern "C" fsim_status fsim_set_tuning(fsim_ctx *c, const fsim_tuning *t, int32_
             r.ket_class > r.bra_class || (r.fp32 != 0 && r.fp32 != 1))
             return fail(FSIM_EINVAL, "tuning record names no quartet class");
         if (r.variant < 0 || r.variant >= ERI_NVARIANT)
-            return fail(FSIM_EINVAL, "variant must be 0..4");
+            return fail(FSIM_EINVAL, "variant must be 0..5");
         if (r.waves_per_block != 1 && r.waves_per_block != 2 && r.waves_per_block != 4)
             return fail(FSIM_EINVAL, "waves_per_block must be 1, 2 or 4");
     }
@@ -1267,20 +1267,22 @@ extern "C" fsim_status fsim_autotune(fsim_ctx *c, const double *D, fsim_precisio
     st = fock_build(c, D, c->F, nullptr, nullptr, nullptr, prec, s);
     for (int v = 0; v < ERI_NVARIANT && st == FSIM_OK; ++v)
         for (int w = 0; w < 3 && st == FSIM_OK; ++w) {
-            if (v == ERI_VARIANT_WAVE && w > 0) continue;   // the wave kernel ignores it
+            if ((v == ERI_VARIANT_WAVE || v == ERI_VARIANT_WIDE) && w > 0) continue;   // one block shape
             // the wave kernel is only a candidate for the high angular-momentum
             // classes (L >= 5) and the ket-outer kernel only for the ss, ps, pp
             // and ds bras;
             // elsewhere those classes keep a lane variant during that pass and
             // are not scored in it
-            const bool wave = v == ERI_VARIANT_WAVE, ko = v == ERI_VARIANT_KO;
+            const bool wave = v == ERI_VARIANT_WAVE, ko = v == ERI_VARIANT_KO,
+                       wide = v == ERI_VARIANT_WIDE;
             auto Ltot = [](int X, int Y) {
                 return pclass_l1(X) + pclass_l2(X) + pclass_l1(Y) + pclass_l2(Y);
             };
             for (int X = 0; X < NPCLASS; ++X)
                 for (int Y = 0; Y < NPCLASS; ++Y)
                     for (int f = 0; f < 2; ++f) {
-                        const bool cand = (!wave || Ltot(X, Y) >= 5) && (!ko || X <= 3);
+                        const bool cand = (!wave || Ltot(X, Y) >= 5) && (!ko || X <= 3) &&
+                                          (!wide || Ltot(X, Y) >= 7);
                         c->variant[X][Y][f] = cand ? v : ERI_DEFAULT_VARIANT;
                         c->wpb[X][Y][f] = wpbs[w];
                     }
@@ -1289,6 +1291,7 @@ extern "C" fsim_status fsim_autotune(fsim_ctx *c, const double *D, fsim_precisio
             for (const auto &r : c->prof)
                 if ((!wave || Ltot(r.bra_class, r.ket_class) >= 5) &&
                     (!ko || r.bra_class <= 3) &&
+                    (!wide || Ltot(r.bra_class, r.ket_class) >= 7) &&
                     r.ms < best[r.bra_class][r.ket_class][r.fp32]) {
                     best[r.bra_class][r.ket_class][r.fp32] = r.ms;
                     bv[r.bra_class][r.ket_class][r.fp32] = v;

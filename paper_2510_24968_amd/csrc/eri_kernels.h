@@ -1001,12 +1001,13 @@ __global__ __launch_bounds__(64) void k_eri_wave(EriArgs a) {
 // fit, or needs more than MAX_CHUNKS chunks, falls back to kernel B.  The
 // autotuner picks a variant and the waves per block for every class and
 // precision.
-constexpr int NVARIANT = 5;
+constexpr int NVARIANT = 6;
 constexpr int VARIANT_WAVE = 3;
 constexpr int VARIANT_KO = 4;
+constexpr int VARIANT_WIDE = 5;   // kernel A at 192 live values, where 160 does not fit
 constexpr int DEFAULT_VARIANT = 1;
 __host__ __device__ constexpr int variant_budget(int v) {
-    return v == 0 ? 96 : (v == 1 ? 128 : (v == 2 ? 160 : 0));
+    return v == 0 ? 96 : (v == 1 ? 128 : (v == 2 ? 160 : (v == VARIANT_WIDE ? 192 : 0)));
 }
 constexpr int MAX_CHUNKS = 24;
 
@@ -1088,6 +1089,14 @@ hipError_t launch_class(bool store, int variant, int wpb, const EriArgs &a, hipS
         case 1: launch_budget<LA, LB, LC, LD, T, false, variant_budget(1)>(ntile, wpb, a, s); break;
         case 2: launch_budget<LA, LB, LC, LD, T, false, variant_budget(2)>(ntile, wpb, a, s); break;
         case VARIANT_KO: launch_ko<LA, LB, LC, LD, T>(ntile, wpb, a, s); break;
+        case VARIANT_WIDE:
+            // only classes whose smallest chunk exceeds 160 live values get a
+            // 192-value lane kernel; every other class runs variant 2
+            if constexpr (!lane_fits<LA, LB, LC, LD, variant_budget(2)>())
+                launch_budget<LA, LB, LC, LD, T, false, variant_budget(VARIANT_WIDE)>(ntile, wpb, a, s);
+            else
+                launch_budget<LA, LB, LC, LD, T, false, variant_budget(2)>(ntile, wpb, a, s);
+            break;
         default: launch_wave_kernel<LA, LB, LC, LD, T, false>(ntile, a, s); break;
     }
     return hipGetLastError();

@@ -72,7 +72,7 @@ class _Tuning(ctypes.Structure):
 
 
 PAIR_CLASS = ("ss", "ps", "pp", "ds", "dp", "dd")
-NVARIANT = 5
+NVARIANT = 6
 
 
 def _struct_dict(s):

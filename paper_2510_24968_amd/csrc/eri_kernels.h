@@ -405,20 +405,33 @@ __global__ __launch_bounds__(256, lane_min_waves(LA, LB, LC, LD, CA, CDC)) void 
                 for (int x = 0; x < NCDc; ++x)
 #pragma unroll
                     for (int h = 0; h < NHAB; ++h) W[x][h] = T(0);
-                // d bras: ket primitive data loaded one primitive ahead of use
-                // (s and p bras load them in place, which measured faster)
+                // d bras: ket primitive data, including this chunk's Hermite box
+                // entries, loaded one primitive ahead of use (s and p bras load
+                // them in place, which measured faster)
+                constexpr int EK0 = box_off(LC, LD, CD0);
+                constexpr int EK1 = CD1 < NCD ? box_off(LC, LD, CD1) : NEK;
+                constexpr int NEKC = STAGE ? EK1 - EK0 : 1;
                 double qn = 0.0, Kxn = 0.0, Kyn = 0.0, Kzn = 0.0;
+                T ekn[NEKC];
                 auto kload = [&](int j_) {
                     qn = a.ket.p[(size_t)j_ * nk + ket];
                     Kxn = a.ket.P[((size_t)j_ * 3 + 0) * nk + ket];
                     Kyn = a.ket.P[((size_t)j_ * 3 + 1) * nk + ket];
                     Kzn = a.ket.P[((size_t)j_ * 3 + 2) * nk + ket];
+                    if constexpr (STAGE) {
+                        const T *__restrict__ ekp = Ek + (size_t)j_ * NEK * nk + ket;
+#pragma unroll
+                        for (int e = 0; e < NEKC; ++e) ekn[e] = ekp[(size_t)(EK0 + e) * nk];
+                    }
                 };
                 if (STAGE && nkp > 0) kload(0);
                 for (int j = 0; j < nkp; ++j) {
                     if (!STAGE) kload(j);
                     const double q = qn;
                     const double X = Px - Kxn, Y = Py - Kyn, Z = Pz - Kzn;
+                    T ekc[NEKC];
+#pragma unroll
+                    for (int e = 0; e < NEKC; ++e) ekc[e] = ekn[e];
                     if (STAGE && j + 1 < nkp) kload(j + 1);
                     // 1/sqrt(p+q) once; 1/(p+q) and alpha = pq/(p+q) from it
                     T src[L + 1];
@@ -464,7 +477,9 @@ __global__ __launch_bounds__(256, lane_min_waves(LA, LB, LC, LD, CA, CDC)) void 
                                 static_for<bz + 1>([&](auto ph_) {
                                     constexpr int ph = decltype(ph_)::value;
                                     constexpr int e = eo + (ta * (by + 1) + nu) * (bz + 1) + ph;
-                                    T ev = ek[(size_t)e * nk];
+                                    T ev;
+                                    if constexpr (STAGE) ev = ekc[e - EK0];
+                                    else ev = ek[(size_t)e * nk];
                                     if constexpr ((ta + nu + ph) & 1) ev = -ev;
                                     static_for<NHAB>([&](auto h_) {
                                         constexpr int h = decltype(h_)::value;

@@ -209,6 +209,61 @@ def test_water10_jk_sampled_elements():
     assert np.max(np.abs(K[mus, nus] - Ke)) < 1e-10
 
 
+def _monomer_density(b):
+    """Block-diagonal density for a water cluster: every molecule's own
+    core-Hamiltonian density from the oracle, zero between molecules (atoms
+    come as O, H, H per molecule, basis functions in atom order)."""
+    from synth.molecules import assemble
+    N = synth.nbf_of(b)
+    D = np.zeros((N, N))
+    off = 0
+    for m in range(len(b["types"]) // 3):
+        Bm = oracle.Basis(assemble(b["types"][3 * m:3 * m + 3], b["xyz"][3 * m:3 * m + 3]))
+        S, T, V = Bm.one_electron()
+        Dm, _, _ = oracle.density_from_fock(T + V, oracle.orthogonalizer(S), Bm.nelec // 2)
+        D[off:off + Bm.nbf, off:off + Bm.nbf] = Dm
+        off += Bm.nbf
+    assert off == N
+    return D
+
+
+def test_water64_bench_configuration_sampled_jk():
+    """The 64-water workload in the launch configuration the benchmark times
+    (committed tuning cache, per-XCD accumulators, FP32 tiles below 1e-5 in
+    the mixed build): sampled J and K elements against the oracle, each from
+    its definition over every unscreened quartet, plus properties that hold
+    at any size (exact symmetry, positive Coulomb and exchange energies for
+    a positive semidefinite density)."""
+    from paper_2510_24968_amd import autotune
+    b, w = synth.workload("water64")
+    ctx = _ctx(b, tau=w["tau"], tau_fp32=w["tau_fp32"])
+    _, st = ctx.schwarz_screen()
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    cache = os.path.join(root, "paper_2510_24968_amd", "tuning", "water64_mi355x.json")
+    assert autotune.apply(ctx, autotune.load(cache)) > 0
+    D = _monomer_density(b)
+    B = oracle.Basis(b)
+    rng = np.random.default_rng(64)
+    xyz = np.asarray(b["xyz"])[0::3]
+    mus, nus = [], []
+    for m in rng.choice(64, 4, replace=False):
+        # one pair inside molecule m, one between m and its nearest neighbour
+        n = int(np.argsort(np.linalg.norm(xyz - xyz[m], axis=1))[1])
+        mus += [21 * m + int(rng.integers(21)), 21 * m + int(rng.integers(21))]
+        nus += [21 * m + int(rng.integers(21)), 21 * n + int(rng.integers(21))]
+    mus, nus = np.array(mus), np.array(nus)
+    Je, Ke = B.jk_elements(D, mus, nus, tau=w["tau"])
+    for prec, tol in (("fp64", 1e-10), ("mixed", 1e-9)):
+        r = ctx.fock_build(_dev(D), prec, want_jk=True)
+        J, K = r["J"].cpu().numpy(), r["K"].cpu().numpy()
+        dJ, dK = np.max(np.abs(J[mus, nus] - Je)), np.max(np.abs(K[mus, nus] - Ke))
+        print(f"water64 {prec} sampled |dJ| = {dJ:.3e}, |dK| = {dK:.3e}", flush=True)
+        assert dJ < tol and dK < tol
+        assert np.array_equal(J, J.T) and np.array_equal(K, K.T)
+        assert np.sum(D * J) > 0 and np.sum(D * K) > 0
+    assert np.max(np.abs(Je)) > 1e-2 and np.max(np.abs(Ke)) > 1e-4     # not a trivial sample
+
+
 # ---------------------------------------------------------------------------
 # SCF
 # ---------------------------------------------------------------------------

@@ -329,6 +329,27 @@ fsim_status fsim_mse(int64_t n, const float *Y, const float *T, const float *mas
 fsim_status fsim_adam(int64_t n, float *w, const float *g, float *m1, float *m2, float lr,
                       float b1, float b2, float eps, int32_t step, uint16_t *wb, void *stream);
 
+/* Fragment packing of a K x N BF16 weight matrix (row-major, ld = N; K a
+ * multiple of 16) for fsim_mlp_forward.  Wp holds (K/16) * ceil(N/16) * 256
+ * BF16 values, caller-allocated: for K step s and column tile t, lane l of
+ * the 16x16x16 MFMA B operand holds rows 16s + 4(l/16) + j (j < 4) of
+ * column 16t + l%16, zero past N, at Wp[((s*ceil(N/16) + t)*64 + l)*4 + j].
+ * FSIM_EINVAL for K <= 0, K % 16 != 0, N <= 0 or NULL pointers. */
+fsim_status fsim_mlp_pack(int32_t K, int32_t N, const uint16_t *W, uint16_t *Wp, void *stream);
+
+/* Fused inference of the guess network (the per-pair MLP of the learned
+ * initial guess): Y = W3^T r(W2^T r(W1^T x + b1) + b2) + b3 per row, r =
+ * ReLU with the hidden activations rounded to BF16, in one kernel that keeps
+ * them in LDS.  The result equals the three fsim_gemm_bf16 calls with
+ * bias/ReLU epilogues bit for bit (same MFMA steps in the same order).
+ * X: n x 64 BF16 row-major (8-byte aligned); W1p, W2p, W3p: fsim_mlp_pack
+ * of W1 (64 x 256), W2 (256 x 256), W3 (256 x 36); b1, b2: FP32 [256],
+ * b3: FP32 [36]; Y: n x 36 FP32 row-major.  n = 0 does nothing; FSIM_EINVAL
+ * for n < 0 or NULL pointers. */
+fsim_status fsim_mlp_forward(int32_t n, const uint16_t *X, const uint16_t *W1p, const float *b1,
+                             const uint16_t *W2p, const float *b2, const uint16_t *W3p,
+                             const float *b3, float *Y, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

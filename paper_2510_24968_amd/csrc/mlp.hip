@@ -6,6 +6,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <type_traits>
 
 #include "../../include/fsim.h"
 
@@ -169,6 +170,127 @@ __global__ void k_adam(size_t n, float *w, const float *__restrict__ g, float *m
     }
 }
 
+// ---------------------------------------------------------------------------
+// Fused inference of the three-layer guess network.  One block of 4 waves
+// takes 32 rows through all three layers; the BF16 hidden activations stay
+// in LDS and are rounded exactly where the layered GEMMs round them, and the
+// K loop runs in the same 16-wide MFMA steps in the same order, so the
+// output equals the layered forward pass bit for bit.  Weights come from
+// global memory (L2-resident, read by every block) pre-packed in MFMA
+// fragment order: one 8-byte load per lane per 16 x 16 B fragment.
+// ---------------------------------------------------------------------------
+constexpr int FR = 32;                          // rows per block
+constexpr int FIN = 64, FH = 256, FOUT = 36;
+constexpr int FXP = FIN + 4, FHP = FH + 4;      // LDS row pitches (BF16): 8-byte rows, skewed banks
+
+// Packed fragment layout of a K x N BF16 matrix (row-major, ld = N): for K
+// step s (16 rows) and column tile t (16 columns), lane l holds rows
+// 16 s + 4 (l / 16) + j, j < 4, of column 16 t + l % 16 (zero past N):
+// Wp[((s * ntile + t) * 64 + l) * 4 + j].
+__global__ void k_pack_frag(int K, int N, const uint16_t *__restrict__ W, uint16_t *Wp) {
+    const int ntile = (N + 15) / 16;
+    const size_t total = (size_t)(K / 16) * ntile * 256;
+    for (size_t x = blockIdx.x * (size_t)blockDim.x + threadIdx.x; x < total;
+         x += (size_t)gridDim.x * blockDim.x) {
+        const int j = x & 3, l = (x >> 2) & 63;
+        const size_t st = x >> 8;
+        const int t = (int)(st % ntile), sk = (int)(st / ntile);
+        const int k = 16 * sk + 4 * (l >> 4) + j, n = 16 * t + (l & 15);
+        Wp[x] = n < N ? W[(size_t)k * N + n] : (uint16_t)0;
+    }
+}
+
+// acc[i][c] += A[row0 + 16 i .., 0..K) W[0..K, 16 (t0 + c) ..) for the
+// wave's NRT row tiles and NCT column tiles; A in LDS (pitch in BF16).
+template <int K, int NRT, int NCT>
+__device__ __forceinline__ void frag_mma(const uint16_t *As, int pitch, int row0,
+                                         const uint16_t *__restrict__ Wp, int ntile, int t0,
+                                         f32x4 (&acc)[NRT][NCT]) {
+    const int lane = threadIdx.x & 63, r16 = lane & 15, kq = (lane >> 4) * 4;
+#pragma unroll
+    for (int i = 0; i < NRT; ++i)
+#pragma unroll
+        for (int c = 0; c < NCT; ++c) acc[i][c] = f32x4{0.f, 0.f, 0.f, 0.f};
+    const bf16x4 *__restrict__ wf = (const bf16x4 *)Wp + (size_t)t0 * 64 + lane;
+#pragma unroll 2
+    for (int s = 0; s < K / 16; ++s) {
+        bf16x4 a[NRT], b[NCT];
+#pragma unroll
+        for (int i = 0; i < NRT; ++i)
+            a[i] = *(const bf16x4 *)(As + (row0 + 16 * i + r16) * pitch + 16 * s + kq);
+#pragma unroll
+        for (int c = 0; c < NCT; ++c) b[c] = wf[((size_t)s * ntile + c) * 64];
+#pragma unroll
+        for (int i = 0; i < NRT; ++i)
+#pragma unroll
+            for (int c = 0; c < NCT; ++c)
+                acc[i][c] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[i], b[c], acc[i][c], 0, 0, 0);
+    }
+}
+
+__global__ __launch_bounds__(256) void k_mlp_forward(int n, const uint16_t *__restrict__ X,
+                                                     const uint16_t *__restrict__ W1p,
+                                                     const float *__restrict__ b1,
+                                                     const uint16_t *__restrict__ W2p,
+                                                     const float *__restrict__ b2,
+                                                     const uint16_t *__restrict__ W3p,
+                                                     const float *__restrict__ b3, float *Y) {
+    __shared__ __align__(16) uint16_t xs[FR * FXP];
+    __shared__ __align__(16) uint16_t h1[FR * FHP];
+    __shared__ __align__(16) uint16_t h2[FR * FHP];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int m0 = blockIdx.x * FR;
+    const int c16 = lane & 15, rq = (lane >> 4) * 4;
+    // input tile, 8 bytes per access; rows past n are zero
+    for (int e = tid; e < FR * (FIN / 4); e += 256) {
+        const int r = e / (FIN / 4), c4 = e % (FIN / 4);
+        uint2 v = {0u, 0u};
+        if (m0 + r < n) v = *(const uint2 *)(X + (size_t)(m0 + r) * FIN + 4 * c4);
+        *(uint2 *)(xs + r * FXP + 4 * c4) = v;
+    }
+    __syncthreads();
+    // hidden layers: wave w owns columns [64 w, 64 w + 64) of all 32 rows
+    auto hidden = [&](const uint16_t *in, int pitch_in, const uint16_t *Wp, const float *bias,
+                      uint16_t *out, auto kdim) {
+        constexpr int K = decltype(kdim)::value;
+        f32x4 acc[FR / 16][4];
+        frag_mma<K, FR / 16, 4>(in, pitch_in, 0, Wp, FH / 16, 4 * wave, acc);
+#pragma unroll
+        for (int i = 0; i < FR / 16; ++i)
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+                const int col = 64 * wave + 16 * c + c16;
+                const float bc = bias[col];
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    float v = acc[i][c][q] + bc;
+                    v = v > 0.f ? v : 0.f;
+                    out[(16 * i + rq + q) * FHP + col] = f2bf(v);
+                }
+            }
+    };
+    hidden(xs, FXP, W1p, b1, h1, std::integral_constant<int, FIN>{});
+    __syncthreads();
+    hidden(h1, FHP, W2p, b2, h2, std::integral_constant<int, FH>{});
+    __syncthreads();
+    // output layer: waves 0 and 1 take one 16-row tile each, 3 column tiles
+    if (wave < FR / 16) {
+        f32x4 acc[1][3];
+        frag_mma<FH, 1, 3>(h2, FHP, 16 * wave, W3p, 3, 0, acc);
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            const int col = 16 * c + c16;
+            if (col >= FOUT) continue;
+            const float bc = b3[col];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int row = m0 + 16 * wave + rq + q;
+                if (row < n) Y[(size_t)row * FOUT + col] = acc[0][c][q] + bc;
+            }
+        }
+    }
+}
+
 static inline dim3 grid1(size_t n) {
     size_t b = (n + 255) / 256;
     if (b > 4096) b = 4096;
@@ -235,5 +357,25 @@ extern "C" fsim_status fsim_adam(int64_t n, float *w, const float *g, float *m1,
     const float c1 = 1.f / (1.f - pb1), c2 = 1.f / (1.f - pb2);
     hipLaunchKernelGGL(k_adam, grid1(n), dim3(256), 0, (hipStream_t)stream, (size_t)n, w, g, m1,
                        m2, lr, b1, b2, eps, c1, c2, wb);
+    return hipGetLastError() == hipSuccess ? FSIM_OK : FSIM_EHIP;
+}
+
+extern "C" fsim_status fsim_mlp_pack(int32_t K, int32_t N, const uint16_t *W, uint16_t *Wp,
+                                     void *stream) {
+    if (K <= 0 || K % 16 || N <= 0 || !W || !Wp) return FSIM_EINVAL;
+    const size_t total = (size_t)(K / 16) * ((N + 15) / 16) * 256;
+    hipLaunchKernelGGL(k_pack_frag, grid1(total), dim3(256), 0, (hipStream_t)stream, K, N, W, Wp);
+    return hipGetLastError() == hipSuccess ? FSIM_OK : FSIM_EHIP;
+}
+
+extern "C" fsim_status fsim_mlp_forward(int32_t n, const uint16_t *X, const uint16_t *W1p,
+                                        const float *b1, const uint16_t *W2p, const float *b2,
+                                        const uint16_t *W3p, const float *b3, float *Y,
+                                        void *stream) {
+    if (n < 0) return FSIM_EINVAL;
+    if (n == 0) return FSIM_OK;
+    if (!X || !W1p || !b1 || !W2p || !b2 || !W3p || !b3 || !Y) return FSIM_EINVAL;
+    hipLaunchKernelGGL(k_mlp_forward, dim3((n + FR - 1) / FR), dim3(256), 0, (hipStream_t)stream,
+                       n, X, W1p, b1, W2p, b2, W3p, b3, Y);
     return hipGetLastError() == hipSuccess ? FSIM_OK : FSIM_EHIP;
 }

@@ -1,6 +1,8 @@
 """Learned initial guess on the GPU, through the C ABI: the BF16 matrix-core
 GEMM against a CPU FP32 product of the same BF16 inputs, the training
 kernels against numpy, forward/backward against the FP64 network oracle,
+the fused three-layer inference kernel against the layered GEMMs (bit for
+bit) and the oracle,
 McWeeny purification against the oracle's, and a small train -> guess ->
 SCF run.
 
@@ -170,6 +172,65 @@ def test_forward_backward_against_oracle():
         a = dW[k].cpu().double().numpy().ravel()
         r = gW64[k].ravel()
         assert a @ r / (np.linalg.norm(a) * np.linalg.norm(r)) > 0.999
+
+
+def _pack_reference(W, K, N):
+    """The fragment order restated in numpy: for K step s, column tile t and
+    lane l, rows 16 s + 4 (l // 16) + j of column 16 t + l % 16 (zero past N)."""
+    nt = (N + 15) // 16
+    out = np.zeros(((K // 16) * nt * 64, 4), dtype=W.dtype)
+    for s_ in range(K // 16):
+        for t in range(nt):
+            for l in range(64):
+                col = 16 * t + l % 16
+                if col < N:
+                    out[(s_ * nt + t) * 64 + l] = W[16 * s_ + 4 * (l // 16) + np.arange(4), col]
+    return out.ravel()
+
+
+@pytest.mark.parametrize("K,N", [(64, 256), (256, 36), (32, 20)])
+def test_mlp_pack_layout(K, N):
+    g = _g()
+    gen = torch.Generator().manual_seed(K + N)
+    Wd, _ = _bf16_pair((K, N), gen)
+    Wp = torch.empty((K // 16) * ((N + 15) // 16) * 256, dtype=torch.int16, device="cuda")
+    g._chk(g._lib().fsim_mlp_pack(K, N, g._p(Wd), g._p(Wp), g._stream()))
+    assert np.array_equal(Wp.cpu().numpy(), _pack_reference(Wd.cpu().numpy(), K, N))
+
+
+@pytest.mark.parametrize("n", [1, 31, 32, 1000, 4099])
+def test_fused_forward_equals_layered_and_oracle(n):
+    """The fused kernel against the three layered GEMMs (bit for bit: same
+    MFMA steps, same rounding points) and against the FP64 network oracle
+    that rounds at the same points; ragged row counts around the 32-row
+    block."""
+    g = _g()
+    print(f"[gpu] fused forward n={n}", flush=True)
+    net, X, _, _ = _net_and_batch(n=n, seed=11)
+    net.b = [torch.randn(b.shape, generator=torch.Generator().manual_seed(k)).cuda() * 0.1
+             for k, b in enumerate(net.b)]          # non-zero biases exercise the epilogues
+    Xb = net.to_bf16(torch.from_numpy(X).cuda())
+    Y_fused = net.infer(Xb)
+    Y_layer = net.forward(Xb)[0]
+    torch.cuda.synchronize()
+    assert torch.equal(Y_fused, Y_layer)
+    W = [w.cpu().double().numpy() for w in net.W]
+    b = [v.cpu().double().numpy() for v in net.b]
+    y16 = omlp.forward(X, W, b, bf16=True)[2]
+    err = np.linalg.norm(Y_fused.cpu().double().numpy() - y16) / np.linalg.norm(y16)
+    assert err < 1e-3
+
+
+def test_fused_forward_rejects_bad_arguments():
+    g = _g()
+    L = g._lib()
+    Y = torch.empty(4, g.NOUT, dtype=torch.float32, device="cuda")
+    assert L.fsim_mlp_forward(-1, None, None, None, None, None, None, None, None, None) != 0
+    assert L.fsim_mlp_forward(0, None, None, None, None, None, None, None, None, None) == 0
+    assert L.fsim_mlp_forward(4, None, None, None, None, None, None, None, g._p(Y), None) != 0
+    W = torch.zeros(20, 8, dtype=torch.int16, device="cuda")
+    assert L.fsim_mlp_pack(20, 8, g._p(W), g._p(W), None) != 0      # K not a multiple of 16
+    assert L.fsim_mlp_pack(16, 0, g._p(W), g._p(W), None) != 0
 
 
 def test_training_reduces_loss():

@@ -334,7 +334,8 @@ fsim_status fsim_adam(int64_t n, float *w, const float *g, float *m1, float *m2,
  * BF16 values, caller-allocated: for K step s and column tile t, lane l of
  * the 16x16x16 MFMA B operand holds rows 16s + 4(l/16) + j (j < 4) of
  * column 16t + l%16, zero past N, at Wp[((s*ceil(N/16) + t)*64 + l)*4 + j].
- * FSIM_EINVAL for K <= 0, K % 16 != 0, N <= 0 or NULL pointers. */
+ * FSIM_EINVAL for K <= 0, K % 16 != 0, N <= 0, NULL pointers or Wp not
+ * 8-byte aligned. */
 fsim_status fsim_mlp_pack(int32_t K, int32_t N, const uint16_t *W, uint16_t *Wp, void *stream);
 
 /* Fused inference of the guess network (the per-pair MLP of the learned
@@ -345,7 +346,7 @@ fsim_status fsim_mlp_pack(int32_t K, int32_t N, const uint16_t *W, uint16_t *Wp,
  * X: n x 64 BF16 row-major (8-byte aligned); W1p, W2p, W3p: fsim_mlp_pack
  * of W1 (64 x 256), W2 (256 x 256), W3 (256 x 36); b1, b2: FP32 [256],
  * b3: FP32 [36]; Y: n x 36 FP32 row-major.  n = 0 does nothing; FSIM_EINVAL
- * for n < 0 or NULL pointers. */
+ * for n < 0, NULL pointers, or X or a packed weight not 8-byte aligned. */
 fsim_status fsim_mlp_forward(int32_t n, const uint16_t *X, const uint16_t *W1p, const float *b1,
                              const uint16_t *W2p, const float *b2, const uint16_t *W3p,
                              const float *b3, float *Y, void *stream);

@@ -363,6 +363,7 @@ extern "C" fsim_status fsim_adam(int64_t n, float *w, const float *g, float *m1,
 extern "C" fsim_status fsim_mlp_pack(int32_t K, int32_t N, const uint16_t *W, uint16_t *Wp,
                                      void *stream) {
     if (K <= 0 || K % 16 || N <= 0 || !W || !Wp) return FSIM_EINVAL;
+    if ((uintptr_t)Wp & 7) return FSIM_EINVAL;      // read back as 8-byte fragments
     const size_t total = (size_t)(K / 16) * ((N + 15) / 16) * 256;
     hipLaunchKernelGGL(k_pack_frag, grid1(total), dim3(256), 0, (hipStream_t)stream, K, N, W, Wp);
     return hipGetLastError() == hipSuccess ? FSIM_OK : FSIM_EHIP;
@@ -375,6 +376,9 @@ extern "C" fsim_status fsim_mlp_forward(int32_t n, const uint16_t *X, const uint
     if (n < 0) return FSIM_EINVAL;
     if (n == 0) return FSIM_OK;
     if (!X || !W1p || !b1 || !W2p || !b2 || !W3p || !b3 || !Y) return FSIM_EINVAL;
+    // the kernel reads X rows and weight fragments 8 bytes at a time
+    for (const void *q : {(const void *)X, (const void *)W1p, (const void *)W2p, (const void *)W3p})
+        if ((uintptr_t)q & 7) return FSIM_EINVAL;
     hipLaunchKernelGGL(k_mlp_forward, dim3((n + FR - 1) / FR), dim3(256), 0, (hipStream_t)stream,
                        n, X, W1p, b1, W2p, b2, W3p, b3, Y);
     return hipGetLastError() == hipSuccess ? FSIM_OK : FSIM_EHIP;

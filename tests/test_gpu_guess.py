@@ -13,6 +13,8 @@ even).  Gradients against the oracle that rounds at the same points as the
 GPU: relative norm error 1e-3 (FP32 accumulation order can flip single BF16
 roundings, each worth 2^-8 relative)."""
 
+import ctypes
+
 import numpy as np
 import pytest
 
@@ -231,6 +233,16 @@ def test_fused_forward_rejects_bad_arguments():
     W = torch.zeros(20, 8, dtype=torch.int16, device="cuda")
     assert L.fsim_mlp_pack(20, 8, g._p(W), g._p(W), None) != 0      # K not a multiple of 16
     assert L.fsim_mlp_pack(16, 0, g._p(W), g._p(W), None) != 0
+    # misaligned input rows or fragments are refused before any launch
+    net = g.GuessNet(seed=0)
+    Wp = net.packed()
+    X = torch.zeros(4 * g.NIN + 1, dtype=torch.int16, device="cuda")
+    odd = ctypes.c_void_p(X.data_ptr() + 2)
+    args = [g._p(Wp[0]), g._p(net.b[0]), g._p(Wp[1]), g._p(net.b[1]), g._p(Wp[2]), g._p(net.b[2]),
+            g._p(Y), None]
+    assert L.fsim_mlp_forward(4, odd, *args) != 0
+    args[2] = ctypes.c_void_p(Wp[1].data_ptr() + 2)
+    assert L.fsim_mlp_forward(4, g._p(X), *args) != 0
 
 
 def test_training_reduces_loss():

@@ -198,6 +198,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-mixed", action="store_true")
+    ap.add_argument("--no-scf", action="store_true", help="skip the SCF runs to convergence")
+    ap.add_argument("--scf-max-iter", type=int, default=40)
     ap.add_argument("--tuning", default=None,
                     help="autotuner cache (JSON); default: the committed one for this workload")
     ap.add_argument("--autotune", action="store_true", help="tune in-process before timing")
@@ -208,6 +210,7 @@ def main():
               file=sys.stderr)
         sys.exit(2)
 
+    import numpy as np
     import torch
     import synth
     from paper_2510_24968_amd import fsim
@@ -363,6 +366,31 @@ def main():
                         "quartets_fp32": st["quartets_fp32"],
                         "speedup_vs_fp64": ms64 / msmx,
                         "fock_build_speedup_vs_fp64": fb["fp64"] / fb["mixed"]}
+    # ERI rates of the FP64 Fock build (median build time)
+    ncart = {"s": 1, "p": 3, "d": 6}
+    cart = sum(r["quartets"] * int(np.prod([ncart[x] for x in r["cls"] if x in ncart]))
+               for r in prof)
+    out["fock_build_fp64_rates"] = {"quartets_per_s": nq / fb["fp64"],
+                                    "prim_quartets_per_s": st["prim_quartets_kept"] / fb["fp64"],
+                                    "cartesian_eris_per_s": cart / fb["fp64"]}
+    if not a.no_scf:
+        # SCF to convergence from the core guess: iteration counts and energies
+        scf = {}
+        for prec in ["fp64"] + ([] if a.no_mixed else ["mixed"]):
+            log(f"{prec} SCF to convergence (at most {a.scf_max_iter} iterations)")
+            torch.cuda.synchronize()
+            t0 = time.time()
+            r = ctx.scf(precision=prec, max_iter=a.scf_max_iter)
+            torch.cuda.synchronize()
+            scf[prec] = {"iterations": r["iterations"], "converged": r["converged"],
+                         "E_total": r["E_total"], "seconds": time.time() - t0}
+            if prec == "mixed":
+                scf[prec]["E_total_mixed_build"] = r["E_total_mixed"]
+            log(f"{prec} SCF: {r['iterations']} iterations, converged {r['converged']}, "
+                f"E={r['E_total']:.10f}")
+        if "mixed" in scf and scf["fp64"]["converged"] and scf["mixed"]["converged"]:
+            scf["mixed"]["dE_vs_fp64_scf_Ha"] = scf["mixed"]["E_total"] - scf["fp64"]["E_total"]
+        out["scf"] = scf
     if not a.no_cpu_baseline:
         log("cpu baseline (oracle sample)")
         out["cpu_baseline"] = cpu_baseline(basis, w, Dfix, a.cpu_seconds)

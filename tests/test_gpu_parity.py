@@ -264,6 +264,44 @@ def test_water64_bench_configuration_sampled_jk():
     assert np.max(np.abs(Je)) > 1e-2 and np.max(np.abs(Ke)) > 1e-4     # not a trivial sample
 
 
+def test_water64_sampled_eri_blocks():
+    """Single contracted blocks at the 64-water geometry: 20,200 shell
+    quartets (10,000 inside pairs of neighbouring molecules, 10,000 anywhere
+    in the cluster for large Boys arguments, 200 (dd|dd) between
+    neighbours), every one of the 21 classes present, against the oracle's
+    Eq. twoe-final."""
+    b, w = synth.workload("water64")
+    ctx = _ctx(b, tau=w["tau"])
+    B = oracle.Basis(b)
+    rng = np.random.default_rng(6400)
+    atom = np.asarray(b["shell_atom"])
+    mol_sh = [np.flatnonzero(atom // 3 == m) for m in range(64)]
+    xyz = np.asarray(b["xyz"])[0::3]
+    near = []
+    for _ in range(10_000):
+        m = int(rng.integers(64))
+        n = int(np.argsort(np.linalg.norm(xyz - xyz[m], axis=1))[rng.integers(1, 4)])
+        pool = np.concatenate([mol_sh[m], mol_sh[n]])
+        near.append(rng.choice(pool, 4))
+    far = rng.integers(0, B.nshell, (10_000, 4))
+    # and (dd|dd), which random draws from 20 shells rarely give
+    dsh = np.flatnonzero(np.asarray(b["shell_l"]) == 2)
+    dd = [dsh[np.argsort(np.linalg.norm(xyz - xyz[m], axis=1))[rng.integers(0, 3, 4)]]
+          for m in rng.integers(0, 64, 200)]
+    quartets = np.concatenate([np.array(near), far, np.array(dd)]).astype(np.int32)
+    def cls(q):
+        bra = tuple(sorted((B.shell_l[q[0]], B.shell_l[q[1]]), reverse=True))
+        ket = tuple(sorted((B.shell_l[q[2]], B.shell_l[q[3]]), reverse=True))
+        return max(bra, ket) + min(bra, ket)
+    assert len({cls(q) for q in quartets}) == 21
+    got = ctx.eri_quartets(quartets)
+    err = np.array([np.max(np.abs(g - B.eri_block(*q))) for g, q in zip(got, quartets)])
+    big = max(np.max(np.abs(g)) for g in got[:10_000])
+    print(f"water64 sampled blocks: max |dERI| = {err.max():.3e}, largest |ERI| = {big:.3f}")
+    assert err.max() < 1e-12
+    assert big > 1.0
+
+
 # ---------------------------------------------------------------------------
 # SCF
 # ---------------------------------------------------------------------------

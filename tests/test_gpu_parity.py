@@ -510,6 +510,58 @@ def test_batch_jk_matches_oracle_per_molecule():
         assert np.max(np.abs(Ks[k].cpu().numpy() - Ko)) < 1e-11, k
 
 
+def test_ch1024_bench_configuration_stratified_molecules():
+    """The 1024-molecule batch in the configuration its benchmark times
+    (committed tuning cache, FP64 and mixed, graph-replayed builds): 16
+    molecules stratified by size carry their oracle core densities (the
+    other blocks are zero).  J and K of the 6 smallest (N <= 56) are
+    compared whole with the oracle's, the 10 larger on 8 sampled elements
+    each; then F from the captured graph, built and replayed, against the
+    oracle's H + J - K/2 at the same elements."""
+    from paper_2510_24968_amd import autotune
+    mols, w = synth.workload("ch1024")
+    bt = _fsim().Batch(mols, tau=w["tau"], tau_fp32=w["tau_fp32"])
+    bt.schwarz_screen()
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    cache = os.path.join(root, "paper_2510_24968_amd", "tuning", "ch1024_mi355x.json")
+    assert autotune.apply(bt, autotune.load(cache)) > 0
+    n = np.array([synth.nbf_of(b) for b in mols])
+    pick = np.argsort(n, kind="stable")[np.linspace(0, len(mols) - 1, 16).astype(int)]
+    blocks = [np.zeros((k, k)) for k in n]
+    ref = {}
+    for m in pick:
+        B = oracle.Basis(mols[m])
+        S, T, V = B.one_electron()
+        blocks[m], _, _ = oracle.density_from_fock(T + V, oracle.orthogonalizer(S), B.nelec // 2)
+        if B.nbf <= 56:
+            mus, nus = np.meshgrid(np.arange(B.nbf), np.arange(B.nbf), indexing="ij")
+            mus, nus = mus.ravel(), nus.ravel()
+            Jo, Ko = B.fock_jk(blocks[m], tau=w["tau"])
+            Je, Ke = Jo[mus, nus], Ko[mus, nus]
+        else:
+            rng = np.random.default_rng(int(m))
+            mus, nus = rng.integers(0, B.nbf, 8), rng.integers(0, B.nbf, 8)
+            Je, Ke = B.jk_elements(blocks[m], mus, nus, tau=w["tau"])
+        ref[m] = (mus, nus, Je, Ke, (T + V)[mus, nus] + Je - 0.5 * Ke)
+    D = bt.pack([_dev(x) for x in blocks])
+    for prec, tol in (("fp64", 1e-11), ("mixed", 1e-9)):
+        r = bt.fock_build(D, prec, want_jk=True)          # eager, with J and K
+        Js, Ks = bt.unpack(r["J"]), bt.unpack(r["K"])
+        worst = max(max(np.max(np.abs(Js[m].cpu().numpy()[ref[m][0], ref[m][1]] - ref[m][2])),
+                        np.max(np.abs(Ks[m].cpu().numpy()[ref[m][0], ref[m][1]] - ref[m][3])))
+                    for m in pick)
+        print(f"ch1024 {prec}: max |dJ|, |dK| over 16 molecules = {worst:.3e}", flush=True)
+        assert worst < tol
+        bt.set_graph(True)
+        for rep in range(2):                               # capture, then replay
+            Fs = bt.unpack(bt.fock_build(D, prec)["F"])
+            worst = max(np.max(np.abs(Fs[m].cpu().numpy()[ref[m][0], ref[m][1]] - ref[m][4]))
+                        for m in pick)
+            print(f"ch1024 {prec} graph build {rep}: max |dF| = {worst:.3e}", flush=True)
+            assert worst < 10 * tol
+        bt.set_graph(False)
+
+
 def test_batch_scf_equals_single_molecule_scf():
     mols = _small_batch()
     kw = dict(conv_rms_dD=1e-9, conv_dE=1e-11)

@@ -565,9 +565,25 @@ def main():
     ap.add_argument("--eval", type=int, default=16)
     ap.add_argument("--epochs", type=int, default=12)
     ap.add_argument("--out", default="guess_out")
+    ap.add_argument("--weights", default=None,
+                    help="evaluate saved weights (guess_weights.npz) instead of training")
+    ap.add_argument("--eval-offset", type=int, default=0,
+                    help="first held-out cluster index (seed 6_000_000 + index)")
     a = ap.parse_args()
     os.makedirs(a.out, exist_ok=True)
     log = lambda s: print(f"[guess] {s}", flush=True)
+    if a.weights:
+        net = GuessNet(seed=0)
+        with np.load(a.weights) as st:
+            net.load({k: st[k] for k in st.files})
+        idx = range(a.eval_offset, a.eval_offset + a.eval)
+        log(f"weights {a.weights}; held-out clusters {idx.start}..{idx.stop - 1}")
+        ev = [synth.water_cluster(32, 6_000_000 + i) for i in idx]
+        res = evaluate(net, ev, log=log)
+        res["eval_indices"] = [idx.start, idx.stop]
+        with open(os.path.join(a.out, "guess_eval.json"), "w") as f:
+            json.dump(res, f, indent=1)
+        return
     t0 = time.time()
     mols = training_molecules(a.chains, a.waters)
     dens, idx = converged_densities(mols, log=log)
@@ -610,7 +626,8 @@ def main():
            "fused_seconds": sec_f, "fused_TFLOP/s": flops / sec_f / 1e12}
     log(f"forward over {nrow} pairs: layered {sec * 1e3:.2f} ms, {fwd['TFLOP/s']:.1f} TFLOP/s; "
         f"fused {sec_f * 1e3:.2f} ms, {fwd['fused_TFLOP/s']:.1f} TFLOP/s (BF16)")
-    ev = [synth.water_cluster(32, 6_000_000 + i) for i in range(a.eval)]
+    ev = [synth.water_cluster(32, 6_000_000 + i)
+          for i in range(a.eval_offset, a.eval_offset + a.eval)]
     res = evaluate(net, ev, log=log)
     res["loss"] = hist
     res["train_molecules"] = len(mols)

@@ -509,10 +509,12 @@ def purify(ctx, D, iters=8):
     return e0.value, e1.value
 
 
-def learned_guess(net, ctx, basis, iters=8, tol=1e-2):
+def learned_guess(net, ctx, basis, iters=24, tol=1e-2):
     """Guess density for a one-molecule context: predicted, purified, and
     replaced by the core-Hamiltonian guess if it stays non-idempotent beyond
-    tol.  Returns (D, info)."""
+    tol.  Returns (D, info).  McWeeny iterations are cheap (three N^3
+    products each); a predicted eigenvalue near 1/2 needs up to about 24 of
+    them to leave the slow region around it."""
     D = torch.tensor(predicted_density(net, basis), dtype=torch.float64, device=ctx.device)
     e0, e1 = purify(ctx, D, iters)
     info = {"idempotency_raw": e0, "idempotency_purified": e1, "fallback": not (e1 <= tol)}

@@ -20,7 +20,11 @@ besides itself; see tests/test_oracle_pins.py):
                   primitive p/d integrals (no E, R or Boys inside), 8-fold
                   symmetry, rotation covariance, translation invariance,
                   the Schwarz inequality.
+  schwarz         pinned: Q_ab^2 equals the largest diagonal element
+                  (mn|mn), m in a, n in b, of the full tensor.
   fock_jk         pinned: literal Eq. fock by einsum over the full tensor.
+  fock_jk_list    pinned: over the whole kept canonical list it equals the
+                  screened fock_jk; disjoint sublists add up to it.
   jk_elements     pinned: agrees with fock_jk element by element.
   scf             pinned: P S P = P, Tr(D S) = N_elec, FDS - SDF = 0 at
                   convergence, two-centre minimal-basis closed form,

@@ -406,6 +406,67 @@ def test_screening_error_is_bounded():
     assert np.max(np.abs(J1 - J0)) > 0
 
 
+@pytest.mark.parametrize("which", ["spd", "water_dimer"])
+def test_schwarz_factor_is_diagonal_tensor_maximum(which):
+    """Q_ab^2 is the largest diagonal integral (mn|mn) over the components
+    m of shell a and n of shell b, read here from the full tensor (each
+    element from its own quartet evaluation)."""
+    basis = spd_molecule() if which == "spd" else synth.water_cluster(2, 1)
+    B = oracle.Basis(basis)
+    g = B.eri_tensor()
+    Q = B.schwarz()
+    N = B.nbf
+    diag = g.reshape(N * N, N * N)[np.arange(N * N), np.arange(N * N)].reshape(N, N)
+    shell_of = np.concatenate([[s] * oracle.NCART[l] for s, l in enumerate(B.shell_l)])
+    for a in range(B.nshell):
+        for b in range(B.nshell):
+            mx = diag[np.ix_(shell_of == a, shell_of == b)].max()
+            assert abs(Q[a, b] ** 2 - mx) <= 1e-14 * mx, (a, b)
+    assert np.max(np.abs(Q - Q.T)) <= 1e-14 * Q.max()
+
+
+def _canonical_quartets(B, Q, tau):
+    """Every canonical shell quartet (a >= b, c >= d, pair (a,b) >= pair
+    (c,d) in lexicographic order) with Q_ab Q_cd >= tau."""
+    pairs = [(a, b) for a in range(B.nshell) for b in range(a + 1)]
+    out = []
+    for i, (a, b) in enumerate(pairs):
+        for c, d in pairs[:i + 1]:
+            if Q[a, b] * Q[c, d] >= tau:
+                out.append((a, b, c, d))
+    return np.array(out, dtype=np.int32)
+
+
+def test_quartet_list_digest_equals_screened_build():
+    """fock_jk_list over the whole kept canonical list of a water trimer is
+    the screened fock_jk, and two disjoint halves of the list add up to it
+    (J and K are linear in the quartet set)."""
+    B = oracle.Basis(synth.water_cluster(3, 2))
+    S, T, V = B.one_electron()
+    X = oracle.orthogonalizer(S)
+    D, _, _ = oracle.density_from_fock(T + V, X, B.nelec // 2)
+    Q = B.schwarz()
+    tau = 1e-9
+    J, K, (kept, total) = B.fock_jk(D, tau, Q, with_counts=True)
+    q = _canonical_quartets(B, Q, tau)
+    npair = B.nshell * (B.nshell + 1) // 2
+    assert len(q) == kept and total == npair * (npair + 1) // 2
+    Jl, Kl = B.fock_jk_list(D, q)
+    scale = max(np.abs(J).max(), np.abs(K).max())
+    assert np.max(np.abs(Jl - J)) <= 1e-13 * scale
+    assert np.max(np.abs(Kl - K)) <= 1e-13 * scale
+    rng = np.random.default_rng(7)
+    pick = rng.random(len(q)) < 0.5
+    J1, K1 = B.fock_jk_list(D, q[pick])
+    J2, K2 = B.fock_jk_list(D, q[~pick])
+    assert np.max(np.abs(J1 + J2 - J)) <= 1e-13 * scale
+    assert np.max(np.abs(K1 + K2 - K)) <= 1e-13 * scale
+    # a quartet listed twice counts twice
+    J3, _ = B.fock_jk_list(D, np.concatenate([q, q[:1]]))
+    J4, _ = B.fock_jk_list(D, q[:1])
+    assert np.max(np.abs(J3 - J - J4)) <= 1e-13 * scale
+
+
 # ---------------------------------------------------------------------------
 # SCF (Sec. 3.2, 3.2.1)
 # ---------------------------------------------------------------------------

@@ -96,7 +96,8 @@ typedef struct {
     int32_t iter;     /* steps taken since create / reset */
     int32_t converged;
     int32_t diis_used;  /* 1 when the DIIS extrapolation was applied */
-    int32_t pad;
+    int32_t full_build; /* 0 when the step's Fock build was incremental */
+    int64_t quartets;   /* contracted shell quartets the step's build evaluated */
 } fsim_scf_info;
 
 /* Message of the last failed call on this thread ("" if none). */
@@ -166,8 +167,40 @@ fsim_status fsim_core_guess(fsim_ctx *ctx, double *D, void *stream);
 fsim_status fsim_scf_step(fsim_ctx *ctx, double *D, fsim_scf_info *info, fsim_precision prec,
                           void *stream);
 
-/* Forget the DIIS history and the step counter. */
+/* Forget the DIIS history, the step counter and the incremental-build
+ * reference. */
 fsim_status fsim_scf_reset(fsim_ctx *ctx);
+
+/* Incremental Fock build (the difference-density refinement of direct SCF,
+ * which the paper names as future work in Sec. 5; J and K are linear in the
+ * density, Eq. fock): with dD = D - D_ref,
+ *   J = J_ref + J[dD],  K = K_ref + K[dD],  F = Hcore + J - K/2,
+ * where J[dD], K[dD] come from the kept quartets (ab|cd) whose
+ * density-weighted bound Q_ab Q_cd max|dD| over the six shell-pair blocks
+ * the digest reads (ab, cd, ac, ad, bc, bd) is >= tau_delta (<= 0: the
+ * screen's tau): each bra's Q-sorted ket range is cut where that bound,
+ * maximised over the rest of the range, falls below tau_delta, so no
+ * skipped quartet changes any digest term by tau_delta or more.
+ * One-molecule contexts only (FSIM_EINVAL for a batch).
+ * D, D_ref, J_ref, K_ref: device N x N (symmetric); J, K: device N x N
+ * outputs, required, and may alias J_ref, K_ref (updated in place); F:
+ * device or NULL; E_elec: host or NULL (synchronises; 1/2 Tr[D (H + F)]);
+ * quartets: host or NULL, receives the number of contracted quartets
+ * evaluated.  The call synchronises the stream once to read the block
+ * maxima of dD back to the host.  FSIM_ESTATE before a screen. */
+fsim_status fsim_fock_build_delta(fsim_ctx *ctx, const double *D, const double *D_ref,
+                                  const double *J_ref, const double *K_ref, double *F, double *J,
+                                  double *K, double *E_elec, double tau_delta, int64_t *quartets,
+                                  fsim_precision prec, void *stream);
+
+/* rebuild_every > 0: fsim_scf_step builds F incrementally from the previous
+ * step's density and J, K (fsim_fock_build_delta with threshold tau_delta,
+ * <= 0 for the screen's tau), with a full build on the first step and then
+ * every rebuild_every steps (info->full_build says which, info->quartets how
+ * many quartets were evaluated).  0 (default): every step runs a full
+ * build.  Allocates the reference D, J, K (3 N x N) on first use;
+ * one-molecule contexts only. */
+fsim_status fsim_set_incremental(fsim_ctx *ctx, int32_t rebuild_every, double tau_delta);
 
 /* Per-launch record of the last profiled Fock build: one entry per quartet
  * class (bra pair class >= ket pair class; 0..5 = ss ps pp ds dp dd) and
@@ -230,7 +263,8 @@ fsim_status fsim_autotune(fsim_ctx *ctx, const double *D, fsim_precision prec, v
 
 /* Contracted ERI blocks (Eq. twoe-final summed over primitives) for n shell
  * quartets, evaluated by the Fock-build kernels but written out instead of
- * digested.  quartets: host [n*4] shell indices (a, b, c, d) in any order.
+ * digested: each quartet class runs the kernel variant and waves per block
+ * currently set for it (fsim_set_tuning), in FP32 for prec = FSIM_MIXED.  quartets: host [n*4] shell indices (a, b, c, d) in any order.
  * offsets: host [n] element offsets into out; block q is written as
  * out[offsets[q] + ((i*nb + j)*nc + k)*nd + l] over Cartesian components.
  * out: device FP64.  Unscreened; works before or after a screen. */

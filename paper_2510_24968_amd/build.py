@@ -20,11 +20,14 @@ HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 
 _PC = ("ss", "ps", "pp", "ds", "dp", "dd")
-ERI_SOURCES = [f"eri_{_PC[b]}{_PC[k]}_{p}.hip" for b in range(6) for k in range(b + 1)
-               for p in ("f64", "f32")]
-# slowest (highest angular momentum) first so the pool stays busy
-SOURCES = ERI_SOURCES[::-1] + ["eri_dispatch.hip", "setup.hip", "linalg.hip", "mlp.hip",
-                                "api.cpp"]
+# eri_class.hip once per (bra pair class, ket pair class, precision): object
+# name -> defines; slowest (highest angular momentum) first so the pool stays busy
+ERI_UNITS = [(f"eri_{_PC[b]}{_PC[k]}_{'f32' if p else 'f64'}",
+              [f"-DFSIM_BRA={b}", f"-DFSIM_KET={k}", f"-DFSIM_FP32={p}"])
+             for b in range(6) for k in range(b + 1) for p in (0, 1)][::-1]
+SOURCES = [("eri_class.hip", name, defs) for name, defs in ERI_UNITS] + [
+    (src, os.path.splitext(src)[0], []) for src in
+    ("eri_dispatch.hip", "setup.hip", "linalg.hip", "mlp.hip", "api.cpp")]
 
 FLAGS = [
     f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC",
@@ -36,28 +39,35 @@ FLAGS = [
 ]
 
 
-def _newest_header():
-    return max(os.path.getmtime(os.path.join(CSRC, f)) for f in os.listdir(CSRC)
-               if f.endswith(".h")) if os.path.isdir(CSRC) else 0.0
+# headers the ERI kernel units include (the other sources may include any)
+ERI_HEADERS = ("eri_kernels.h", "boys.h", "fsim_internal.h")
 
 
-def _compile(src, verbose, incremental=False):
-    obj = os.path.join(BUILD, os.path.splitext(src)[0] + ".o")
+def _newest_header(src):
+    names = ERI_HEADERS if src == "eri_class.hip" else [
+        f for f in os.listdir(CSRC) if f.endswith(".h")]
+    return max(os.path.getmtime(os.path.join(CSRC, f)) for f in names)
+
+
+def _compile(unit, verbose, incremental=False):
+    src, name, defs = unit
+    obj = os.path.join(BUILD, name + ".o")
     if incremental and os.path.exists(obj):
         t = os.path.getmtime(obj)
-        deps = max(os.path.getmtime(os.path.join(CSRC, src)), _newest_header(),
-                   os.path.getmtime(os.path.join(ROOT, "include", "fsim.h")))
+        deps = max(os.path.getmtime(os.path.join(CSRC, src)), _newest_header(src))
+        if src != "eri_class.hip":
+            deps = max(deps, os.path.getmtime(os.path.join(ROOT, "include", "fsim.h")))
         if t > deps:
             return obj
-    cmd = [HIPCC] + FLAGS + ["-c", os.path.join(CSRC, src), "-o", obj]
+    cmd = [HIPCC] + FLAGS + defs + ["-c", os.path.join(CSRC, src), "-o", obj]
     if src.endswith(".cpp"):
-        cmd = [HIPCC] + FLAGS + ["-x", "hip", "-c", os.path.join(CSRC, src), "-o", obj]
+        cmd = [HIPCC] + FLAGS + defs + ["-x", "hip", "-c", os.path.join(CSRC, src), "-o", obj]
     t0 = time.time()
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
-        raise RuntimeError(f"hipcc failed for {src}:\n{r.stdout}\n{r.stderr}")
+        raise RuntimeError(f"hipcc failed for {name}:\n{r.stdout}\n{r.stderr}")
     if verbose:
-        print(f"  {src}: {time.time() - t0:.1f}s", flush=True)
+        print(f"  {name}: {time.time() - t0:.1f}s", flush=True)
     return obj
 
 

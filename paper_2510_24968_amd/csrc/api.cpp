@@ -54,9 +54,20 @@ struct ListStats {
     int64_t nq = 0, npq = 0;
     double flops = 0.0, flops_exec = 0.0;
 };
+// Host copy of a tile list's bra records and ket ranges.
+struct HostList {
+    std::vector<int> bra, lo, hi;
+};
 struct ClassLists {
     TileList all64, mix64, mix32;
     ListStats s64, sm64, sm32;
+    // incremental builds: host copies of the three lists (all64, mix64,
+    // mix32) and lists of the same bra records with density-screened ket
+    // ends (own tile_start / ket_hi; bra and ket_lo shared)
+    HostList host[3];
+    TileList delta[3];
+    std::vector<int> dstart[3], dhi[3];
+    int64_t dnq[3] = {0, 0, 0};
 };
 
 struct DevPool {
@@ -140,6 +151,19 @@ struct fsim_ctx {
     // per-XCD private J'/K' accumulators (NXCD copies of each), summed after the build
     bool xcd_private = true;
     double *priv = nullptr;
+    // incremental builds (one molecule): shell of each basis function,
+    // D - Dref, per-shell-pair max |D - Dref| (device and host), the kept
+    // pairs' shells per class
+    int *d_bf_shell = nullptr;
+    double *dD = nullptr, *Mblk = nullptr;
+    std::vector<double> Mhost;
+    std::vector<int> kept_s1[NPCLASS], kept_s2[NPCLASS];
+    // SCF with incremental builds: full build every inc_every steps, the
+    // reference density and its J, K
+    int inc_every = 0, inc_count = 0;
+    bool inc_have = false;
+    double inc_tau = 0.0;   // density-weighted threshold (<= 0: the screen's tau)
+    double *Dref = nullptr, *Jref = nullptr, *Kref = nullptr;
     double *eig = nullptr, *ework = nullptr, *scal = nullptr;
     int *dinfo = nullptr;
     rocblas_handle blas = nullptr;
@@ -492,7 +516,15 @@ static fsim_status create_impl(const fsim_basis *mols, int nmol, const fsim_opti
         if (rocblas_daxpy(c->blas, (int)P, &one, c->T2, 1, c->H, 1) != rocblas_status_success)
             return cleanup(fail(FSIM_EHIP, "rocblas_daxpy failed"));
     }
-    c->pool.release(dbs);
+    if (nmol == 1) {
+        // incremental builds read the shell of every basis function
+        c->d_bf_shell = dbs;
+        PCHK(c->pool.alloc(&c->dD, P));
+        PCHK(c->pool.alloc(&c->Mblk, (size_t)c->nshell * c->nshell));
+        c->Mhost.assign((size_t)c->nshell * c->nshell, 0.0);
+    } else {
+        c->pool.release(dbs);
+    }
     c->pool.release(dbc);
 
     const int m_hist = std::max(1, c->opt.diis_m);
@@ -641,9 +673,11 @@ struct StoreTask {
 }  // namespace
 
 // Run the store kernels for tasks grouped by (bra class, ket class) on the
-// all-pairs tables.
+// all-pairs tables: with tuned, each class runs the kernel variant and block
+// shape its Fock build uses (the same kernel code writing blocks out instead
+// of digesting them); otherwise the default variant.
 static fsim_status run_store(fsim_ctx *c, std::vector<StoreTask> (&tasks)[NPCLASS][NPCLASS],
-                             double *out, bool fp32, hipStream_t s) {
+                             double *out, bool fp32, bool tuned, hipStream_t s) {
     for (int X = 0; X < NPCLASS; ++X)
         for (int Y = 0; Y <= X; ++Y) {
             auto &tv = tasks[X][Y];
@@ -694,7 +728,9 @@ static fsim_status run_store(fsim_ctx *c, std::vector<StoreTask> (&tasks)[NPCLAS
             a.out = out;
             a.boys = c->boys;
             a.nbf = c->nbf;
-            HIPCHK(launch_eri(X, Y, fp32, true, ERI_DEFAULT_VARIANT, 4, a, s));
+            const int f = fp32 ? 1 : 0;
+            HIPCHK(launch_eri(X, Y, fp32, true, tuned ? c->variant[X][Y][f] : ERI_DEFAULT_VARIANT,
+                              tuned ? c->wpb[X][Y][f] : 4, a, s));
             HIPCHK(hipStreamSynchronize(s));
             hipFree(dbra);
             hipFree(dket);
@@ -751,7 +787,7 @@ extern "C" fsim_status fsim_eri_quartets(fsim_ctx *c, int64_t n, const int32_t *
         t.st[3] = stv[kh][1];
         tasks[pc[bh]][pc[kh]].push_back(t);
     }
-    return run_store(c, tasks, out, prec == FSIM_MIXED, (hipStream_t)stream);
+    return run_store(c, tasks, out, prec == FSIM_MIXED, true, (hipStream_t)stream);
 }
 
 // ---------------------------------------------------------------------------
@@ -850,7 +886,7 @@ extern "C" fsim_status fsim_schwarz_screen(fsim_ctx *c, double tau, double tau32
     }
     double *dblk = nullptr;
     HIPCHK(hipMalloc(&dblk, sizeof(double) * std::max<long long>(1, base[NPCLASS])));
-    STCHK(run_store(c, tasks, dblk, false, nullptr));
+    STCHK(run_store(c, tasks, dblk, false, false, nullptr));
     std::vector<double> blk(base[NPCLASS]);
     HIPCHK(hipMemcpy(blk.data(), dblk, sizeof(double) * blk.size(), hipMemcpyDeviceToHost));
     hipFree(dblk);
@@ -897,7 +933,9 @@ extern "C" fsim_status fsim_schwarz_screen(fsim_ctx *c, double tau, double tau32
             if (ma != mb) return ma < mb;
             return Qpair[pc][a] > Qpair[pc][b];
         });
-        std::vector<int> s1, s2;
+        std::vector<int> &s1 = c->kept_s1[pc], &s2 = c->kept_s2[pc];
+        s1.clear();
+        s2.clear();
         c->Qkept[pc].clear();
         seg[pc].assign(c->nmol + 1, 0);
         for (int i : order[pc]) {
@@ -972,6 +1010,22 @@ extern "C" fsim_status fsim_schwarz_screen(fsim_ctx *c, double tau, double tau32
             STCHK(upload_list(c->screen_pool, cl.all64, b64, lo64, hi64));
             STCHK(upload_list(c->screen_pool, cl.mix64, bm64, lom64, him64));
             STCHK(upload_list(c->screen_pool, cl.mix32, bm32, lom32, him32));
+            cl.host[0] = HostList{b64, lo64, hi64};
+            cl.host[1] = HostList{bm64, lom64, him64};
+            cl.host[2] = HostList{bm32, lom32, him32};
+            const TileList *full[3] = {&cl.all64, &cl.mix64, &cl.mix32};
+            for (int k = 0; k < 3; ++k) {
+                TileList &d = cl.delta[k];
+                d = *full[k];
+                d.ntile = 0;
+                d.nquartet = 0;
+                cl.dnq[k] = 0;
+                cl.dstart[k].assign(d.nbra + 1, 0);
+                cl.dhi[k] = cl.host[k].lo;
+                if (d.nbra == 0) continue;
+                HIPCHK(c->screen_pool.alloc(&d.tile_start, (size_t)d.nbra + 1));
+                HIPCHK(c->screen_pool.alloc(&d.ket_hi, (size_t)d.nbra));
+            }
             S.quartets_kept += cl.all64.nquartet;
             // primitive quartets: sum over kept quartets of K_bra * K_ket
             std::vector<int> kb(Qb.size()), kk(Qk.size());
@@ -1012,6 +1066,7 @@ extern "C" fsim_status fsim_schwarz_screen(fsim_ctx *c, double tau, double tau32
     c->tau32 = tau32;
     c->stats = S;
     c->screened = true;
+    c->inc_have = false;
     if (Q_out)
         HIPCHK(hipMemcpy(Q_out, c->Qmat.data(), sizeof(double) * ns * ns, hipMemcpyHostToDevice));
     if (stats) *stats = S;
@@ -1037,18 +1092,32 @@ static void drop_graphs(fsim_ctx *c) {
 
 static constexpr int NXCD = 8;   // XCDs of an MI355X
 
+// acc (optional): one shared pair of J'/K' accumulators to use instead of
+// the context's own (the allocation-free entry point).
+struct AccPair {
+    double *J, *K;
+};
+
+// dref (optional): an incremental build over the density-screened lists;
+// D is then D - Dref and J, K (required) become Jref + J[D], Kref + K[D].
+struct DeltaRefs {
+    const double *J, *K;
+};
+
 static fsim_status enqueue_build(fsim_ctx *c, const double *D, double *F, double *J, double *K,
                                  bool mixed, std::vector<fsim_class_profile> *prof,
-                                 hipStream_t s) {
+                                 hipStream_t s, const AccPair *acc = nullptr,
+                                 const DeltaRefs *dref = nullptr) {
     const size_t P = (size_t)c->packed;
-    const bool xp = c->xcd_private && c->priv;
-    double *Jacc = xp ? c->priv : c->Jh;
-    double *Kacc = xp ? c->priv + NXCD * P : c->Kh;
+    const bool xp = !acc && c->xcd_private && c->priv;
+    double *Jsum = acc ? acc->J : c->Jh, *Ksum = acc ? acc->K : c->Kh;
+    double *Jacc = xp ? c->priv : Jsum;
+    double *Kacc = xp ? c->priv + NXCD * P : Ksum;
     if (xp) {
         HIPCHK(fill(c->priv, 2 * NXCD * P, 0.0, s));
     } else {
-        HIPCHK(fill(c->Jh, P, 0.0, s));
-        HIPCHK(fill(c->Kh, P, 0.0, s));
+        HIPCHK(fill(Jsum, P, 0.0, s));
+        HIPCHK(fill(Ksum, P, 0.0, s));
     }
     int nev = 0;
     // heaviest classes (highest L) first
@@ -1056,19 +1125,23 @@ static fsim_status enqueue_build(fsim_ctx *c, const double *D, double *F, double
         for (int Y = X; Y >= 0; --Y) {
             ClassLists &cl = c->lists[X][Y];
             for (int part = 0; part < (mixed ? 2 : 1); ++part) {
-                const TileList &tl = mixed ? (part == 0 ? cl.mix64 : cl.mix32) : cl.all64;
+                const int li = mixed ? 1 + part : 0;
+                const TileList &tl = dref ? cl.delta[li]
+                                          : (mixed ? (part == 0 ? cl.mix64 : cl.mix32) : cl.all64);
                 if (tl.ntile == 0) continue;
                 if (prof) {
                     const ListStats &ls = mixed ? (part == 0 ? cl.sm64 : cl.sm32) : cl.s64;
+                    // delta lists: model counts scaled by the evaluated share
+                    const double share = dref ? (double)cl.dnq[li] / std::max<int64_t>(1, ls.nq) : 1.0;
                     fsim_class_profile pr{};
                     pr.bra_class = X;
                     pr.ket_class = Y;
                     pr.fp32 = mixed && part == 1;
                     pr.tiles = tl.ntile;
-                    pr.quartets = ls.nq;
-                    pr.prim_quartets = ls.npq;
-                    pr.flops = ls.flops;
-                    pr.flops_exec = ls.flops_exec;
+                    pr.quartets = dref ? cl.dnq[li] : ls.nq;
+                    pr.prim_quartets = (int64_t)(ls.npq * share);
+                    pr.flops = ls.flops * share;
+                    pr.flops_exec = ls.flops_exec * share;
                     prof->push_back(pr);
                     HIPCHK(hipEventRecord(c->ev[nev++], s));
                 }
@@ -1091,10 +1164,27 @@ static fsim_status enqueue_build(fsim_ctx *c, const double *D, double *F, double
             }
         }
     if (xp) {
-        HIPCHK(sum_copies(P, NXCD, c->priv, P, c->Jh, s));
-        HIPCHK(sum_copies(P, NXCD, c->priv + NXCD * P, P, c->Kh, s));
+        HIPCHK(sum_copies(P, NXCD, c->priv, P, Jsum, s));
+        HIPCHK(sum_copies(P, NXCD, c->priv + NXCD * P, P, Ksum, s));
     }
-    HIPCHK(assemble_fock_packed(layout_of(c), c->Jh, c->Kh, c->H, F, J, K, s));
+    if (dref)
+        HIPCHK(assemble_delta(layout_of(c), Jsum, Ksum, c->H, dref->J, dref->K, F, J, K, s));
+    else
+        HIPCHK(assemble_fock_packed(layout_of(c), Jsum, Ksum, c->H, F, J, K, s));
+    return FSIM_OK;
+}
+
+// E_elec = 1/2 Tr[D (H + F)] summed over the molecules (synchronises s).
+static fsim_status electronic_energy(fsim_ctx *c, const double *D, const double *F, double *E,
+                                     hipStream_t s) {
+    HIPCHK(fill(c->Emol, c->nmol, 0.0, s));
+    HIPCHK(dot3_packed(layout_of(c), D, c->H, F, 0.5, c->Emol, s));
+    HIPCHK(hipMemcpyAsync(c->Emol_host.data(), c->Emol, sizeof(double) * c->nmol,
+                          hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    double e = 0.0;
+    for (double v : c->Emol_host) e += v;
+    *E = e;
     return FSIM_OK;
 }
 
@@ -1156,14 +1246,7 @@ static fsim_status fock_build(fsim_ctx *c, const double *D, double *F, double *J
     }
     if (E_elec) {
         if (!F) return fail(FSIM_EINVAL, "E_elec needs F");
-        HIPCHK(fill(c->Emol, c->nmol, 0.0, s));
-        HIPCHK(dot3_packed(layout_of(c), D, c->H, F, 0.5, c->Emol, s));
-        HIPCHK(hipMemcpyAsync(c->Emol_host.data(), c->Emol, sizeof(double) * c->nmol,
-                              hipMemcpyDeviceToHost, s));
-        HIPCHK(hipStreamSynchronize(s));
-        double e = 0.0;
-        for (double v : c->Emol_host) e += v;
-        *E_elec = e;
+        STCHK(electronic_energy(c, D, F, E_elec, s));
     }
     return FSIM_OK;
 }
@@ -1175,6 +1258,154 @@ extern "C" fsim_status fsim_fock_build(fsim_ctx *c, const double *D, double *F, 
     double *Fo = F;
     if (!Fo && E_elec) Fo = c->F;
     return fock_build(c, D, Fo, J, K, E_elec, prec, s);
+}
+
+// ---------------------------------------------------------------------------
+// Incremental (difference-density) Fock build
+// ---------------------------------------------------------------------------
+
+// Density-screened ket ends for every tile list, from M (host, per shell
+// pair max |dD|).  A kept quartet (ab|cd) reads dD only in the blocks ab, cd,
+// ac, ad, bc and bd, each bounded by max(m_ab, M_cd, R_c, R_d) with R_x the
+// largest M in shell row x and m_ab = max(M_ab, R_a, R_b).  With the kets of a
+// class Q-sorted, w_k = Q_k max(M_cd, R_c, R_d) and its suffix maximum SW_k,
+// every ket j >= k of bra i has Q_i Q_j max|dD blocks| <= Q_i max(SW_k,
+// m_i Q_k); the first k where that falls below thr ends the bra's range, so
+// only quartets whose density-weighted bound is below thr are skipped.
+static fsim_status delta_lists(fsim_ctx *c, double thr, hipStream_t s, int64_t *nq_total) {
+    const int ns = c->nshell;
+    const std::vector<double> &M = c->Mhost;
+    std::vector<double> R(ns, 0.0);
+    for (int a = 0; a < ns; ++a)
+        for (int b = 0; b < ns; ++b) R[a] = std::max(R[a], M[(size_t)a * ns + b]);
+    std::vector<double> mpair[NPCLASS], SW[NPCLASS];
+    for (int pc = 0; pc < NPCLASS; ++pc) {
+        const size_t n = c->Qkept[pc].size();
+        mpair[pc].resize(n);
+        SW[pc].assign(n + 1, 0.0);
+        for (size_t k = 0; k < n; ++k) {
+            const int x = c->kept_s1[pc][k], y = c->kept_s2[pc][k];
+            mpair[pc][k] = std::max(M[(size_t)x * ns + y], std::max(R[x], R[y]));
+        }
+        for (size_t k = n; k-- > 0;)
+            SW[pc][k] = std::max(SW[pc][k + 1], c->Qkept[pc][k] * mpair[pc][k]);
+    }
+    int64_t total = 0;
+    for (int X = 0; X < NPCLASS; ++X)
+        for (int Y = 0; Y <= X; ++Y) {
+            ClassLists &cl = c->lists[X][Y];
+            const std::vector<double> &Qb = c->Qkept[X], &Qk = c->Qkept[Y];
+            for (int li = 0; li < 3; ++li) {
+                const HostList &h = cl.host[li];
+                TileList &d = cl.delta[li];
+                std::vector<int> &st = cl.dstart[li], &hi = cl.dhi[li];
+                int64_t nq = 0;
+                for (size_t r = 0; r < h.bra.size(); ++r) {
+                    const int i = h.bra[r];
+                    const double qi = Qb[i], mi = mpair[X][i];
+                    int lo = h.lo[r], up = h.hi[r];
+                    // first ket whose bound (and every later one's) is below tau
+                    while (lo < up) {
+                        const int k = (lo + up) / 2;
+                        if (qi * std::max(SW[Y][k], mi * Qk[k]) >= thr) lo = k + 1;
+                        else up = k;
+                    }
+                    hi[r] = lo;
+                    const int nk = lo - h.lo[r];
+                    nq += nk;
+                    st[r + 1] = st[r] + (nk + TILE - 1) / TILE;
+                }
+                d.ntile = h.bra.empty() ? 0 : st.back();
+                d.nquartet = nq;
+                cl.dnq[li] = nq;
+                if (!h.bra.empty()) {
+                    HIPCHK(hipMemcpyAsync(d.tile_start, st.data(), sizeof(int) * st.size(),
+                                          hipMemcpyHostToDevice, s));
+                    HIPCHK(hipMemcpyAsync(d.ket_hi, hi.data(), sizeof(int) * hi.size(),
+                                          hipMemcpyHostToDevice, s));
+                }
+                if (li == 0) total += nq;
+            }
+        }
+    *nq_total = total;
+    return FSIM_OK;
+}
+
+static fsim_status fock_build_delta_impl(fsim_ctx *c, const double *D, const double *Dref,
+                                         const double *Jref, const double *Kref, double *F,
+                                         double *J, double *K, double *E_elec, double tau_delta,
+                                         int64_t *quartets, fsim_precision prec, hipStream_t s) {
+    if (c->nmol != 1) return fail(FSIM_EINVAL, "incremental builds are for one-molecule contexts");
+    if (!c->screened) return fail(FSIM_ESTATE, "fsim_schwarz_screen must run before a Fock build");
+    if (!D || !Dref || !Jref || !Kref || !J || !K)
+        return fail(FSIM_EINVAL, "D, D_ref, J_ref, K_ref, J and K must not be NULL");
+    if (E_elec && !F) return fail(FSIM_EINVAL, "E_elec needs F");
+    if (!std::isfinite(tau_delta)) return fail(FSIM_EINVAL, "tau_delta must be finite");
+    const double thr = tau_delta > 0 ? tau_delta : c->tau;
+    const bool mixed = prec == FSIM_MIXED && c->tau32 > 0;
+    const int N = c->nbf, ns = c->nshell;
+    HIPCHK(fill(c->Mblk, (size_t)ns * ns, 0.0, s));
+    HIPCHK(delta_blockmax(N, D, Dref, c->dD, c->d_bf_shell, ns, c->Mblk, s));
+    HIPCHK(hipMemcpyAsync(c->Mhost.data(), c->Mblk, sizeof(double) * c->Mhost.size(),
+                          hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    int64_t nq = 0;
+    STCHK(delta_lists(c, thr, s, &nq));
+    if (mixed) {
+        nq = 0;
+        for (int X = 0; X < NPCLASS; ++X)
+            for (int Y = 0; Y <= X; ++Y) nq += c->lists[X][Y].dnq[1] + c->lists[X][Y].dnq[2];
+    }
+    if (c->profiling && c->ev.empty()) {
+        c->ev.resize(2 * 2 * NPCLASS * NPCLASS);
+        for (auto &e : c->ev) HIPCHK(hipEventCreate(&e));
+    }
+    if (c->xcd_private && !c->priv) HIPCHK(c->pool.alloc(&c->priv, 2 * NXCD * (size_t)c->packed));
+    std::vector<fsim_class_profile> prof;
+    const DeltaRefs dref{Jref, Kref};
+    STCHK(enqueue_build(c, c->dD, F, J, K, mixed, c->profiling ? &prof : nullptr, s, nullptr,
+                        &dref));
+    if (c->profiling) {
+        HIPCHK(hipStreamSynchronize(s));
+        for (size_t k = 0; k < prof.size(); ++k) {
+            float ms = 0.f;
+            HIPCHK(hipEventElapsedTime(&ms, c->ev[2 * k], c->ev[2 * k + 1]));
+            prof[k].ms = ms;
+        }
+        c->prof = prof;
+    }
+    if (quartets) *quartets = nq;
+    if (E_elec) STCHK(electronic_energy(c, D, F, E_elec, s));
+    return FSIM_OK;
+}
+
+extern "C" fsim_status fsim_fock_build_delta(fsim_ctx *c, const double *D, const double *Dref,
+                                             const double *Jref, const double *Kref, double *F,
+                                             double *J, double *K, double *E_elec,
+                                             double tau_delta, int64_t *quartets,
+                                             fsim_precision prec, void *stream) {
+    if (!c) return fail(FSIM_EINVAL, "ctx is NULL");
+    return fock_build_delta_impl(c, D, Dref, Jref, Kref, F, J, K, E_elec, tau_delta, quartets,
+                                 prec, (hipStream_t)stream);
+}
+
+extern "C" fsim_status fsim_set_incremental(fsim_ctx *c, int32_t rebuild_every, double tau_delta) {
+    if (!c) return fail(FSIM_EINVAL, "ctx is NULL");
+    if (rebuild_every < 0) return fail(FSIM_EINVAL, "rebuild_every must be >= 0");
+    if (!std::isfinite(tau_delta)) return fail(FSIM_EINVAL, "tau_delta must be finite");
+    c->inc_tau = tau_delta;
+    if (rebuild_every > 0 && c->nmol != 1)
+        return fail(FSIM_EINVAL, "incremental builds are for one-molecule contexts");
+    if (rebuild_every > 0 && !c->Dref) {
+        const size_t P = (size_t)c->packed;
+        HIPCHK(c->pool.alloc(&c->Dref, P));
+        HIPCHK(c->pool.alloc(&c->Jref, P));
+        HIPCHK(c->pool.alloc(&c->Kref, P));
+    }
+    c->inc_every = rebuild_every;
+    c->inc_have = false;
+    c->inc_count = 0;
+    return FSIM_OK;
 }
 
 extern "C" fsim_status fsim_set_profiling(fsim_ctx *c, int32_t enable) {
@@ -1335,6 +1566,8 @@ extern "C" fsim_status fsim_scf_reset(fsim_ctx *c) {
     for (auto &r : c->mol_info) r = fsim_scf_info{};
     c->iter = 0;
     c->have_prev = false;
+    c->inc_have = false;
+    c->inc_count = 0;
     return FSIM_OK;
 }
 
@@ -1392,7 +1625,25 @@ extern "C" fsim_status fsim_scf_step(fsim_ctx *c, double *D, fsim_scf_info *info
     const int N = c->nbf;
     const size_t N2 = (size_t)N * N;
     double Eel = 0.0;
-    STCHK(fock_build(c, D, c->F, nullptr, nullptr, &Eel, prec, s));
+    int full = 1;
+    int64_t nq = prec == FSIM_MIXED && c->tau32 > 0 ? c->stats.quartets_fp64 + c->stats.quartets_fp32
+                                                    : c->stats.quartets_kept;
+    if (c->inc_every > 0) {
+        if (c->inc_have && c->inc_count < c->inc_every) {
+            // F(D) = H + Jref + J[D - Dref] - (Kref + K[D - Dref]) / 2, in place
+            STCHK(fock_build_delta_impl(c, D, c->Dref, c->Jref, c->Kref, c->F, c->Jref, c->Kref,
+                                        &Eel, c->inc_tau, &nq, prec, s));
+            full = 0;
+            c->inc_count += 1;
+        } else {
+            STCHK(fock_build(c, D, c->F, c->Jref, c->Kref, &Eel, prec, s));
+            c->inc_have = true;
+            c->inc_count = 1;
+        }
+        HIPCHK(hipMemcpyAsync(c->Dref, D, sizeof(double) * N2, hipMemcpyDeviceToDevice, s));
+    } else {
+        STCHK(fock_build(c, D, c->F, nullptr, nullptr, &Eel, prec, s));
+    }
     BLASCHK(rocblas_set_stream(c->blas, s));
     // e = F D S - S D F = A - A^T with A = F D S (symmetric F, D, S)
     STCHK(gemm(c->blas, false, false, N, N, N, 1.0, c->F, N, D, N, 0.0, c->T1, N));
@@ -1449,6 +1700,8 @@ extern "C" fsim_status fsim_scf_step(fsim_ctx *c, double *D, fsim_scf_info *info
     info->comm_norm = comm;
     info->iter = c->iter;
     info->diis_used = used;
+    info->full_build = full;
+    info->quartets = nq;
     info->converged = info->rms_dD < c->opt.conv_rms_dD &&
                       (c->opt.conv_dE <= 0 || (c->have_prev && std::fabs(info->dE) < c->opt.conv_dE));
     c->have_prev = true;
@@ -1554,6 +1807,9 @@ static fsim_status batched_scf_step(fsim_ctx *c, double *D, fsim_scf_info *info,
     fsim_scf_info agg{};
     agg.iter = c->iter;
     agg.converged = 1;
+    agg.full_build = 1;
+    agg.quartets = prec == FSIM_MIXED && c->tau32 > 0 ? c->stats.quartets_fp64 + c->stats.quartets_fp32
+                                                      : c->stats.quartets_kept;
     for (int m = 0; m < nm; ++m) {
         fsim_scf_info &r = c->mol_info[m];
         const double E = c->Emol_host[m] + c->mol_enuc[m];
@@ -1564,6 +1820,7 @@ static fsim_status batched_scf_step(fsim_ctx *c, double *D, fsim_scf_info *info,
         r.comm_norm = comm[m];
         r.iter = c->iter;
         r.diis_used = used[m];
+        r.full_build = 1;
         r.converged = r.rms_dD < c->opt.conv_rms_dD &&
                       (c->opt.conv_dE <= 0 || (c->have_prev && std::fabs(r.dE) < c->opt.conv_dE));
         c->Eprev_mol[m] = E;

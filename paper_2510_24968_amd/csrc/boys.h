@@ -10,7 +10,8 @@
 //     F_{n-1} = (2 T F_n + exp(-T)) / (2n - 1).
 // For T >= BOYS_TMAX, F_0 = sqrt(pi / T) / 2 (erfc(sqrt T) < 1e-16 there)
 // and the upward recursion F_{n+1} = ((2n + 1) F_n - exp(-T)) / (2T), which
-// is stable for 2T > 2n + 1.  Everything here is FP64.
+// is stable for 2T > 2n + 1.  Everything here is FP64 except the Taylor
+// step of boys_eval_mixed (FP32 tiles).
 #pragma once
 
 #include "fsim_internal.h"
@@ -61,10 +62,13 @@ __device__ __forceinline__ void boys_eval(double T, const double *tab, double *F
     }
 }
 
-// FP32 evaluation for the FP32 tiles (quartets whose Schwarz bound is below
-// the FP32 threshold): the same grid rounded to FP32 and 5 Taylor terms (the
-// truncation, at most 0.05^5/5! relative to F_L, is below FP32 rounding),
-// with the hardware single-precision exp and reciprocal square root.
+// Evaluation for the FP32 tiles (quartets whose Schwarz bound is below the
+// FP32 threshold).  Only the small-T Taylor step runs in FP32: the same grid
+// rounded to FP32 and 5 Taylor terms (truncation at most 0.05^5/5! relative
+// to F_L, below FP32 rounding), which gives F_L to FP32 accuracy.  The
+// downward recursion to F_0..F_{L-1} and the whole large-T branch
+// (asymptotic F_0 and the upward recursion) stay FP64; the caller rounds
+// the R^n_000 sources to FP32 afterwards.
 constexpr int BOYS_NTAYLOR32 = 5;
 constexpr int BOYS_LDS32 = BOYS_NT * BOYS_NTAYLOR32;
 
@@ -78,25 +82,25 @@ __device__ inline void boys_stage32(float *lds, const double *__restrict__ g, in
 }
 
 template <int L>
-__device__ __forceinline__ void boys_eval32(float T, const float *tab, float *F) {
-    if (T < (float)BOYS_TMAX) {
-        const int k = __float2int_rn(T * (float)BOYS_INV_DT);
-        const float d = k * (float)BOYS_DT - T;
+__device__ __forceinline__ void boys_eval_mixed(double T, const float *tab, double *F) {
+    if (T < BOYS_TMAX) {
+        const float Tf = (float)T;
+        const int k = __float2int_rn(Tf * (float)BOYS_INV_DT);
+        const float d = k * (float)BOYS_DT - Tf;
         const float *c = tab + k * BOYS_NTAYLOR32;
         float f = c[BOYS_NTAYLOR32 - 1];
 #pragma unroll
         for (int j = BOYS_NTAYLOR32 - 2; j >= 0; --j) f = fmaf(f, d, c[j]);
-        F[L] = f;
+        F[L] = (double)f;
         if constexpr (L > 0) {
-            const float e = __expf(-T), t2 = 2.0f * T;
+            const double e = exp(-T), t2 = 2.0 * T;
 #pragma unroll
-            for (int n = L; n > 0; --n) F[n - 1] = fmaf(t2, F[n], e) * (1.0f / (2 * n - 1));
+            for (int n = L; n > 0; --n) F[n - 1] = fma(t2, F[n], e) * (1.0 / (2 * n - 1));
         }
     } else {
-        const float r = rsqrtf(T);
-        F[0] = 0.886226925f * r;
+        F[0] = 0.88622692545275801365 * rsqrt(T);   // sqrt(pi)/2 / sqrt(T)
         if constexpr (L > 0) {
-            const float e = __expf(-T), h = 0.5f * r * r;
+            const double e = exp(-T), h = 0.5 / T;
 #pragma unroll
             for (int n = 0; n < L; ++n) F[n + 1] = ((2 * n + 1) * F[n] - e) * h;
         }

@@ -1,140 +1,31 @@
-// Quartet-class dispatch table over the per-class kernel files.
+// Quartet-class dispatch: (bra pair class, ket pair class, precision) -> the
+// explicit instantiation of launch_eri_unit compiled from eri_class.hip.
 #include "fsim_internal.h"
 
 namespace fsim {
 
-hipError_t launch_eri_ssss_f64(bool store, int variant, int wpb,
-                               const EriArgs &a, hipStream_t s);
-hipError_t launch_eri_ssss_f32(bool store, int variant, int wpb,
-                               const EriArgs &a, hipStream_t s);
-hipError_t launch_eri_psss_f64(bool store, int variant, int wpb,
-                               const EriArgs &a, hipStream_t s);
-hipError_t launch_eri_psss_f32(bool store, int variant, int wpb,
-                               const EriArgs &a, hipStream_t s);
-hipError_t launch_eri_psps_f64(bool store, int variant, int wpb,
-                               const EriArgs &a, hipStream_t s);
-hipError_t launch_eri_psps_f32(bool store, int variant, int wpb,
-                               const EriArgs &a, hipStream_t s);
-hipError_t launch_eri_ppss_f64(bool store, int variant, int wpb,
-                               const EriArgs &a, hipStream_t s);
-hipError_t launch_eri_ppss_f32(bool store, int variant, int wpb,
-                               const EriArgs &a, hipStream_t s);
-hipError_t launch_eri_ppps_f64(bool store, int variant, int wpb,
-                               const EriArgs &a, hipStream_t s);
-hipError_t launch_eri_ppps_f32(bool store, int variant, int wpb,
-                               const EriArgs &a, hipStream_t s);
-hipError_t launch_eri_pppp_f64(bool store, int variant, int wpb,
-                               const EriArgs &a, hipStream_t s);
-hipError_t launch_eri_pppp_f32(bool store, int variant, int wpb,
-                               const EriArgs &a, hipStream_t s);
-hipError_t launch_eri_dsss_f64(bool store, int variant, int wpb,
-                               const EriArgs &a, hipStream_t s);
-hipError_t launch_eri_dsss_f32(bool store, int variant, int wpb,
-                               const EriArgs &a, hipStream_t s);
-hipError_t launch_eri_dsps_f64(bool store, int variant, int wpb,
-                               const EriArgs &a, hipStream_t s);
-hipError_t launch_eri_dsps_f32(bool store, int variant, int wpb,
-                               const EriArgs &a, hipStream_t s);
-hipError_t launch_eri_dspp_f64(bool store, int variant, int wpb,
-                               const EriArgs &a, hipStream_t s);
-hipError_t launch_eri_dspp_f32(bool store, int variant, int wpb,
-                               const EriArgs &a, hipStream_t s);
-hipError_t launch_eri_dsds_f64(bool store, int variant, int wpb,
-                               const EriArgs &a, hipStream_t s);
-hipError_t launch_eri_dsds_f32(bool store, int variant, int wpb,
-                               const EriArgs &a, hipStream_t s);
-hipError_t launch_eri_dpss_f64(bool store, int variant, int wpb,
-                               const EriArgs &a, hipStream_t s);
-hipError_t launch_eri_dpss_f32(bool store, int variant, int wpb,
-                               const EriArgs &a, hipStream_t s);
-hipError_t launch_eri_dpps_f64(bool store, int variant, int wpb,
-                               const EriArgs &a, hipStream_t s);
-hipError_t launch_eri_dpps_f32(bool store, int variant, int wpb,
-                               const EriArgs &a, hipStream_t s);
-hipError_t launch_eri_dppp_f64(bool store, int variant, int wpb,
-                               const EriArgs &a, hipStream_t s);
-hipError_t launch_eri_dppp_f32(bool store, int variant, int wpb,
-                               const EriArgs &a, hipStream_t s);
-hipError_t launch_eri_dpds_f64(bool store, int variant, int wpb,
-                               const EriArgs &a, hipStream_t s);
-hipError_t launch_eri_dpds_f32(bool store, int variant, int wpb,
-                               const EriArgs &a, hipStream_t s);
-hipError_t launch_eri_dpdp_f64(bool store, int variant, int wpb,
-                               const EriArgs &a, hipStream_t s);
-hipError_t launch_eri_dpdp_f32(bool store, int variant, int wpb,
-                               const EriArgs &a, hipStream_t s);
-hipError_t launch_eri_ddss_f64(bool store, int variant, int wpb,
-                               const EriArgs &a, hipStream_t s);
-hipError_t launch_eri_ddss_f32(bool store, int variant, int wpb,
-                               const EriArgs &a, hipStream_t s);
-hipError_t launch_eri_ddps_f64(bool store, int variant, int wpb,
-                               const EriArgs &a, hipStream_t s);
-hipError_t launch_eri_ddps_f32(bool store, int variant, int wpb,
-                               const EriArgs &a, hipStream_t s);
-hipError_t launch_eri_ddpp_f64(bool store, int variant, int wpb,
-                               const EriArgs &a, hipStream_t s);
-hipError_t launch_eri_ddpp_f32(bool store, int variant, int wpb,
-                               const EriArgs &a, hipStream_t s);
-hipError_t launch_eri_ddds_f64(bool store, int variant, int wpb,
-                               const EriArgs &a, hipStream_t s);
-hipError_t launch_eri_ddds_f32(bool store, int variant, int wpb,
-                               const EriArgs &a, hipStream_t s);
-hipError_t launch_eri_dddp_f64(bool store, int variant, int wpb,
-                               const EriArgs &a, hipStream_t s);
-hipError_t launch_eri_dddp_f32(bool store, int variant, int wpb,
-                               const EriArgs &a, hipStream_t s);
-hipError_t launch_eri_dddd_f64(bool store, int variant, int wpb,
-                               const EriArgs &a, hipStream_t s);
-hipError_t launch_eri_dddd_f32(bool store, int variant, int wpb,
-                               const EriArgs &a, hipStream_t s);
+template <int X, int Y>
+static hipError_t unit(bool fp32, bool store, int variant, int wpb, const EriArgs &a,
+                       hipStream_t s) {
+    return fp32 ? launch_eri_unit<X, Y, true>(store, variant, wpb, a, s)
+                : launch_eri_unit<X, Y, false>(store, variant, wpb, a, s);
+}
 
 hipError_t launch_eri(int bra_pc, int ket_pc, bool fp32, bool store, int variant, int wpb,
                       const EriArgs &a, hipStream_t s) {
-    switch (bra_pc * 8 + ket_pc) {
-        case 0: return fp32 ? launch_eri_ssss_f32(store, variant, wpb, a, s)
-                         : launch_eri_ssss_f64(store, variant, wpb, a, s);
-        case 8: return fp32 ? launch_eri_psss_f32(store, variant, wpb, a, s)
-                         : launch_eri_psss_f64(store, variant, wpb, a, s);
-        case 9: return fp32 ? launch_eri_psps_f32(store, variant, wpb, a, s)
-                         : launch_eri_psps_f64(store, variant, wpb, a, s);
-        case 16: return fp32 ? launch_eri_ppss_f32(store, variant, wpb, a, s)
-                         : launch_eri_ppss_f64(store, variant, wpb, a, s);
-        case 17: return fp32 ? launch_eri_ppps_f32(store, variant, wpb, a, s)
-                         : launch_eri_ppps_f64(store, variant, wpb, a, s);
-        case 18: return fp32 ? launch_eri_pppp_f32(store, variant, wpb, a, s)
-                         : launch_eri_pppp_f64(store, variant, wpb, a, s);
-        case 24: return fp32 ? launch_eri_dsss_f32(store, variant, wpb, a, s)
-                         : launch_eri_dsss_f64(store, variant, wpb, a, s);
-        case 25: return fp32 ? launch_eri_dsps_f32(store, variant, wpb, a, s)
-                         : launch_eri_dsps_f64(store, variant, wpb, a, s);
-        case 26: return fp32 ? launch_eri_dspp_f32(store, variant, wpb, a, s)
-                         : launch_eri_dspp_f64(store, variant, wpb, a, s);
-        case 27: return fp32 ? launch_eri_dsds_f32(store, variant, wpb, a, s)
-                         : launch_eri_dsds_f64(store, variant, wpb, a, s);
-        case 32: return fp32 ? launch_eri_dpss_f32(store, variant, wpb, a, s)
-                         : launch_eri_dpss_f64(store, variant, wpb, a, s);
-        case 33: return fp32 ? launch_eri_dpps_f32(store, variant, wpb, a, s)
-                         : launch_eri_dpps_f64(store, variant, wpb, a, s);
-        case 34: return fp32 ? launch_eri_dppp_f32(store, variant, wpb, a, s)
-                         : launch_eri_dppp_f64(store, variant, wpb, a, s);
-        case 35: return fp32 ? launch_eri_dpds_f32(store, variant, wpb, a, s)
-                         : launch_eri_dpds_f64(store, variant, wpb, a, s);
-        case 36: return fp32 ? launch_eri_dpdp_f32(store, variant, wpb, a, s)
-                         : launch_eri_dpdp_f64(store, variant, wpb, a, s);
-        case 40: return fp32 ? launch_eri_ddss_f32(store, variant, wpb, a, s)
-                         : launch_eri_ddss_f64(store, variant, wpb, a, s);
-        case 41: return fp32 ? launch_eri_ddps_f32(store, variant, wpb, a, s)
-                         : launch_eri_ddps_f64(store, variant, wpb, a, s);
-        case 42: return fp32 ? launch_eri_ddpp_f32(store, variant, wpb, a, s)
-                         : launch_eri_ddpp_f64(store, variant, wpb, a, s);
-        case 43: return fp32 ? launch_eri_ddds_f32(store, variant, wpb, a, s)
-                         : launch_eri_ddds_f64(store, variant, wpb, a, s);
-        case 44: return fp32 ? launch_eri_dddp_f32(store, variant, wpb, a, s)
-                         : launch_eri_dddp_f64(store, variant, wpb, a, s);
-        case 45: return fp32 ? launch_eri_dddd_f32(store, variant, wpb, a, s)
-                         : launch_eri_dddd_f64(store, variant, wpb, a, s);
+#define FSIM_UNIT(X, Y) \
+    case X * NPCLASS + Y: return unit<X, Y>(fp32, store, variant, wpb, a, s);
+    switch (bra_pc * NPCLASS + ket_pc) {
+        FSIM_UNIT(0, 0)
+        FSIM_UNIT(1, 0) FSIM_UNIT(1, 1)
+        FSIM_UNIT(2, 0) FSIM_UNIT(2, 1) FSIM_UNIT(2, 2)
+        FSIM_UNIT(3, 0) FSIM_UNIT(3, 1) FSIM_UNIT(3, 2) FSIM_UNIT(3, 3)
+        FSIM_UNIT(4, 0) FSIM_UNIT(4, 1) FSIM_UNIT(4, 2) FSIM_UNIT(4, 3) FSIM_UNIT(4, 4)
+        FSIM_UNIT(5, 0) FSIM_UNIT(5, 1) FSIM_UNIT(5, 2) FSIM_UNIT(5, 3) FSIM_UNIT(5, 4)
+        FSIM_UNIT(5, 5)
         default: return hipErrorInvalidValue;
     }
+#undef FSIM_UNIT
 }
 
 }  // namespace fsim

@@ -288,7 +288,8 @@ __global__ __launch_bounds__(256, lane_min_waves(LA, LB, LC, LD, CA, CDC)) void 
     constexpr int NCD = NC * ND, NHAB = nherm(LAB), NH = nherm(L);
     constexpr int NEB = n_entries(LA, LB), NEK = n_entries(LC, LD);
     constexpr int NCHA = (NA + CA - 1) / CA, NCHCD = (NCD + CDC - 1) / CDC;
-    // Boys grid in LDS: FP64 for FP64 tiles, FP32 (5 terms) for FP32 tiles
+    // Boys grid in LDS: FP64 for FP64 tiles, FP32 (5 terms, the Taylor step
+    // only) for FP32 tiles
     constexpr bool F32 = std::is_same<T, float>::value;
     __shared__ std::conditional_t<F32, float, double> tab[F32 ? BOYS_LDS32 : BOYS_LDS];
     extern __shared__ __align__(16) unsigned char stage_lds[];
@@ -436,18 +437,17 @@ __global__ __launch_bounds__(256, lane_min_waves(LA, LB, LC, LD, CA, CDC)) void 
                     // 1/sqrt(p+q) once; 1/(p+q) and alpha = pq/(p+q) from it
                     T src[L + 1];
                     if constexpr (F32) {
-                        // FP32 tile: prefactor, Boys and sources in FP32
-                        const float pf = (float)p, qf = (float)q;
-                        const float Xf = (float)X, Yf = (float)Y, Zf = (float)Z;
-                        const float rsf = rsqrtf(pf + qf);
-                        const float al = pf * qf * (rsf * rsf);
-                        float F[L + 1];
-                        boys_eval32<L>(al * (Xf * Xf + Yf * Yf + Zf * Zf), tab, F);
-                        float m = rsf;
+                        // FP32 tile: FP32 Taylor step, FP64 recursion and
+                        // prefactor, sources rounded to FP32
+                        const double rs = rsqrt(p + q);
+                        const double alpha = p * q * (rs * rs);
+                        double F[L + 1];
+                        boys_eval_mixed<L>(alpha * (X * X + Y * Y + Z * Z), tab, F);
+                        double m = rs;
 #pragma unroll
                         for (int n = 0; n <= L; ++n) {
-                            src[n] = F[n] * m;
-                            m *= -2.0f * al;
+                            src[n] = (float)(F[n] * m);
+                            m *= -2.0 * alpha;
                         }
                     } else {
                         const double rs = rsqrt(p + q);
@@ -541,7 +541,7 @@ __global__ __launch_bounds__(256, lane_min_waves(LA, LB, LC, LD, CA, CDC)) void 
 }
 
 // ===========================================================================
-// Kernel A, ket-outer order (ss, ps, pp and ds bras, Fock mode).  The same lane-per-
+// Kernel A, ket-outer order (ss, ps, pp and ds bras; Fock or store mode).  The same lane-per-
 // quartet tiles as k_eri_lane, with the primitive loops swapped: each ket
 // primitive's data are loaded once and held in registers while the bra
 // primitives (staged in LDS for the whole wave) run inside, and the bra
@@ -552,14 +552,15 @@ __global__ __launch_bounds__(256, lane_min_waves(LA, LB, LC, LD, CA, CDC)) void 
 // quartet (cheap for small bra boxes) against loading every ket primitive
 // once per quartet instead of once per bra primitive.
 // ===========================================================================
-template <int LA, int LB, int LC, int LD, typename T, int CA, int CDC>
+template <int LA, int LB, int LC, int LD, typename T, bool STORE, int CA, int CDC>
 __global__ __launch_bounds__(256) void k_eri_lane_ko(EriArgs a) {
     constexpr int L = LA + LB + LC + LD, LAB = LA + LB;
     constexpr int NA = ncart(LA), NB = ncart(LB), NC = ncart(LC), ND = ncart(LD);
     constexpr int NCD = NC * ND, NHAB = nherm(LAB), NH = nherm(L);
     constexpr int NEB = n_entries(LA, LB), NEK = n_entries(LC, LD);
     constexpr int NCHA = (NA + CA - 1) / CA, NCHCD = (NCD + CDC - 1) / CDC;
-    // Boys grid in LDS: FP64 for FP64 tiles, FP32 (5 terms) for FP32 tiles
+    // Boys grid in LDS: FP64 for FP64 tiles, FP32 (5 terms, the Taylor step
+    // only) for FP32 tiles
     constexpr bool F32 = std::is_same<T, float>::value;
     __shared__ std::conditional_t<F32, float, double> tab[F32 ? BOYS_LDS32 : BOYS_LDS];
     extern __shared__ __align__(16) unsigned char stage_lds[];
@@ -568,11 +569,11 @@ __global__ __launch_bounds__(256) void k_eri_lane_ko(EriArgs a) {
     __syncthreads();
     const int lane = threadIdx.x & 63;
     const int wpb = blockDim.x >> 6;
-    const int ntile = a.tl.ntile;
+    const int ntile = STORE ? a.st_ntile : a.tl.ntile;
     const T *__restrict__ Eb = etab<T>(a.bra);
     const T *__restrict__ Ek = etab<T>(a.ket);
     const size_t nb = a.bra.n, nk = a.ket.n;
-    const long long xoff = a.xcd_stride ? xcd_index() * a.xcd_stride : 0;
+    const long long xoff = (!STORE && a.xcd_stride) ? xcd_index() * a.xcd_stride : 0;
     // every bra primitive of the tile is staged (the launch checks kmax fits)
     double *__restrict__ sp = (double *)(stage_lds + (size_t)(threadIdx.x >> 6) * a.stage_bytes);
     T *__restrict__ se = (T *)(sp + 4 * a.stage_prims);
@@ -580,20 +581,29 @@ __global__ __launch_bounds__(256) void k_eri_lane_ko(EriArgs a) {
     for (int tile0 = blockIdx.x * wpb + (threadIdx.x >> 6); tile0 < ntile;
          tile0 += gridDim.x * wpb) {
         const int tile = __builtin_amdgcn_readfirstlane(tile0);
-        const int b = tile_bra(a.tl, tile);
-        const int bra = __builtin_amdgcn_readfirstlane(a.tl.bra[b]);
-        const int k0 = a.tl.ket_lo[b] + (tile - a.tl.tile_start[b]) * TILE;
-        int ket = k0 + lane;
-        const bool active = ket < a.tl.ket_hi[b];
-        if (!active) ket = k0;
+        int bra, ket;
+        bool active;
+        if constexpr (STORE) {
+            bra = __builtin_amdgcn_readfirstlane(a.st_bra[tile]);
+            ket = a.st_ket[tile * 64 + lane];
+            active = ket >= 0;
+            if (!active) ket = 0;
+        } else {
+            const int b = tile_bra(a.tl, tile);
+            bra = __builtin_amdgcn_readfirstlane(a.tl.bra[b]);
+            const int k0 = a.tl.ket_lo[b] + (tile - a.tl.tile_start[b]) * TILE;
+            ket = k0 + lane;
+            active = ket < a.tl.ket_hi[b];
+            if (!active) ket = k0;
+        }
         const int nbp = __builtin_amdgcn_readfirstlane(a.bra.nprim[bra]);
         const int nkp = active ? a.ket.nprim[ket] : 0;
         const int mol = __builtin_amdgcn_readfirstlane(a.bra.mol[bra]);
-        const long long mbase = a.mol_off[mol];
-        const int N = a.mol_n[mol];
-        const double *__restrict__ D = a.D + mbase;
-        double *__restrict__ Jh = a.Jh + xoff + mbase;
-        double *__restrict__ Kh = a.Kh + xoff + mbase;
+        const long long mbase = STORE ? 0 : a.mol_off[mol];
+        const int N = STORE ? 0 : a.mol_n[mol];
+        const double *__restrict__ D = STORE ? nullptr : a.D + mbase;
+        double *__restrict__ Jh = STORE ? nullptr : a.Jh + xoff + mbase;
+        double *__restrict__ Kh = STORE ? nullptr : a.Kh + xoff + mbase;
         const int f1 = __builtin_amdgcn_readfirstlane(a.bra.bf1[bra]);
         const int f2 = __builtin_amdgcn_readfirstlane(a.bra.bf2[bra]);
         const int f3 = a.ket.bf1[ket], f4 = a.ket.bf2[ket];
@@ -601,6 +611,18 @@ __global__ __launch_bounds__(256) void k_eri_lane_ko(EriArgs a) {
         if (a.bra.sh1[bra] == a.bra.sh2[bra]) fac *= 0.5;
         if (a.ket.sh1[ket] == a.ket.sh2[ket]) fac *= 0.5;
         if (a.same_class && ket == bra) fac *= 0.5;
+        long long soff = 0;
+        int st0 = 0, st1 = 0, st2 = 0, st3 = 0;
+        if constexpr (STORE) {
+            if (active) {
+                const size_t q = (size_t)tile * 64 + lane;
+                soff = a.st_off[q];
+                st0 = a.st_stride[q * 4 + 0];
+                st1 = a.st_stride[q * 4 + 1];
+                st2 = a.st_stride[q * 4 + 2];
+                st3 = a.st_stride[q * 4 + 3];
+            }
+        }
 
         // stage the bra primitives: p, P (4 doubles) and the Hermite boxes
         for (int x = lane; x < nbp * 4; x += 64) {
@@ -644,18 +666,17 @@ __global__ __launch_bounds__(256) void k_eri_lane_ko(EriArgs a) {
                                  Z = sp[i * 4 + 3] - Kz;
                     T src[L + 1];
                     if constexpr (F32) {
-                        // FP32 tile: prefactor, Boys and sources in FP32
-                        const float pf = (float)p, qf = (float)q;
-                        const float Xf = (float)X, Yf = (float)Y, Zf = (float)Z;
-                        const float rsf = rsqrtf(pf + qf);
-                        const float al = pf * qf * (rsf * rsf);
-                        float F[L + 1];
-                        boys_eval32<L>(al * (Xf * Xf + Yf * Yf + Zf * Zf), tab, F);
-                        float m = rsf;
+                        // FP32 tile: FP32 Taylor step, FP64 recursion and
+                        // prefactor, sources rounded to FP32
+                        const double rs = rsqrt(p + q);
+                        const double alpha = p * q * (rs * rs);
+                        double F[L + 1];
+                        boys_eval_mixed<L>(alpha * (X * X + Y * Y + Z * Z), tab, F);
+                        double m = rs;
 #pragma unroll
                         for (int n = 0; n <= L; ++n) {
-                            src[n] = F[n] * m;
-                            m *= -2.0f * al;
+                            src[n] = (float)(F[n] * m);
+                            m *= -2.0 * alpha;
                         }
                     } else {
                         const double rs = rsqrt(p + q);
@@ -725,8 +746,23 @@ __global__ __launch_bounds__(256) void k_eri_lane_ko(EriArgs a) {
                     });
                 }
             }
-            digest_chunk<LA, LB, LC, LD, T, A0, A1, CD0, CD1>(out, D, Jh, Kh, N, f1, f2, f3, f4, fac,
-                                                              active);
+            if constexpr (STORE) {
+                if (active) {
+                    static_for<NABc>([&](auto abl_) {
+                        constexpr int abl = decltype(abl_)::value;
+                        constexpr int ia = A0 + abl / NB, ib = abl % NB;
+                        static_for<NCDc>([&](auto cdl_) {
+                            constexpr int cdl = decltype(cdl_)::value;
+                            constexpr int ic = (CD0 + cdl) / ND, id = (CD0 + cdl) % ND;
+                            a.out[soff + ia * st0 + ib * st1 + ic * st2 + id * st3] =
+                                (double)out[abl][cdl];
+                        });
+                    });
+                }
+            } else {
+                digest_chunk<LA, LB, LC, LD, T, A0, A1, CD0, CD1>(out, D, Jh, Kh, N, f1, f2, f3,
+                                                                  f4, fac, active);
+            }
         });
     }
 }
@@ -1068,7 +1104,7 @@ void launch_budget(int ntile, int wpb, const EriArgs &a, hipStream_t s) {
     }
 }
 
-template <int LA, int LB, int LC, int LD, typename T>
+template <int LA, int LB, int LC, int LD, typename T, bool STORE>
 void launch_ko(int ntile, int wpb, const EriArgs &a, hipStream_t s) {
     constexpr int BUDGET = variant_budget(DEFAULT_VARIANT);
     if constexpr (n_entries(LA, LB) <= KO_MAX_BRA_BOX && lane_fits<LA, LB, LC, LD, BUDGET>()) {
@@ -1081,12 +1117,33 @@ void launch_ko(int ntile, int wpb, const EriArgs &a, hipStream_t s) {
             b.stage_bytes = (kmax * per_prim + 15) / 16 * 16;
             int blocks = (ntile + wpb - 1) / wpb;
             if (blocks > 8192) blocks = 8192;
-            hipLaunchKernelGGL((k_eri_lane_ko<LA, LB, LC, LD, T, CA, CDC>), dim3(blocks),
+            hipLaunchKernelGGL((k_eri_lane_ko<LA, LB, LC, LD, T, STORE, CA, CDC>), dim3(blocks),
                                dim3(64 * wpb), (size_t)wpb * b.stage_bytes, s, b);
             return;
         }
     }
-    launch_budget<LA, LB, LC, LD, T, false, BUDGET>(ntile, wpb, a, s);
+    launch_budget<LA, LB, LC, LD, T, STORE, BUDGET>(ntile, wpb, a, s);
+}
+
+// One variant in Fock mode (STORE = false) or store mode (the same kernel
+// code writing the contracted blocks out instead of digesting them).
+template <int LA, int LB, int LC, int LD, typename T, bool STORE>
+void launch_variant(int ntile, int variant, int wpb, const EriArgs &a, hipStream_t s) {
+    switch (variant) {
+        case 0: launch_budget<LA, LB, LC, LD, T, STORE, variant_budget(0)>(ntile, wpb, a, s); break;
+        case 1: launch_budget<LA, LB, LC, LD, T, STORE, variant_budget(1)>(ntile, wpb, a, s); break;
+        case 2: launch_budget<LA, LB, LC, LD, T, STORE, variant_budget(2)>(ntile, wpb, a, s); break;
+        case VARIANT_KO: launch_ko<LA, LB, LC, LD, T, STORE>(ntile, wpb, a, s); break;
+        case VARIANT_WIDE:
+            // only classes whose smallest chunk exceeds 160 live values get a
+            // 192-value lane kernel; every other class runs variant 2
+            if constexpr (!lane_fits<LA, LB, LC, LD, variant_budget(2)>())
+                launch_budget<LA, LB, LC, LD, T, STORE, variant_budget(VARIANT_WIDE)>(ntile, wpb, a, s);
+            else
+                launch_budget<LA, LB, LC, LD, T, STORE, variant_budget(2)>(ntile, wpb, a, s);
+            break;
+        default: launch_wave_kernel<LA, LB, LC, LD, T, STORE>(ntile, a, s); break;
+    }
 }
 
 template <int LA, int LB, int LC, int LD, typename T>
@@ -1094,26 +1151,8 @@ hipError_t launch_class(bool store, int variant, int wpb, const EriArgs &a, hipS
     const int ntile = store ? a.st_ntile : a.tl.ntile;
     if (ntile <= 0) return hipSuccess;
     if (wpb < 1 || wpb > 4) wpb = 4;
-    if (store) {
-        // stored blocks (screening, per-integral checks) use the default variant
-        launch_budget<LA, LB, LC, LD, T, true, variant_budget(DEFAULT_VARIANT)>(ntile, wpb, a, s);
-        return hipGetLastError();
-    }
-    switch (variant) {
-        case 0: launch_budget<LA, LB, LC, LD, T, false, variant_budget(0)>(ntile, wpb, a, s); break;
-        case 1: launch_budget<LA, LB, LC, LD, T, false, variant_budget(1)>(ntile, wpb, a, s); break;
-        case 2: launch_budget<LA, LB, LC, LD, T, false, variant_budget(2)>(ntile, wpb, a, s); break;
-        case VARIANT_KO: launch_ko<LA, LB, LC, LD, T>(ntile, wpb, a, s); break;
-        case VARIANT_WIDE:
-            // only classes whose smallest chunk exceeds 160 live values get a
-            // 192-value lane kernel; every other class runs variant 2
-            if constexpr (!lane_fits<LA, LB, LC, LD, variant_budget(2)>())
-                launch_budget<LA, LB, LC, LD, T, false, variant_budget(VARIANT_WIDE)>(ntile, wpb, a, s);
-            else
-                launch_budget<LA, LB, LC, LD, T, false, variant_budget(2)>(ntile, wpb, a, s);
-            break;
-        default: launch_wave_kernel<LA, LB, LC, LD, T, false>(ntile, a, s); break;
-    }
+    if (store) launch_variant<LA, LB, LC, LD, T, true>(ntile, variant, wpb, a, s);
+    else launch_variant<LA, LB, LC, LD, T, false>(ntile, variant, wpb, a, s);
     return hipGetLastError();
 }
 

@@ -98,8 +98,10 @@ __host__ __device__ constexpr int n_entries(int l1, int l2) {
 __host__ __device__ constexpr int pclass(int l1, int l2) {   // l1 >= l2
     return l1 * (l1 + 1) / 2 + l2;
 }
-inline int pclass_l1(int pc) { return pc < 1 ? 0 : (pc < 3 ? 1 : 2); }
-inline int pclass_l2(int pc) { return pc - pclass(pclass_l1(pc), 0); }
+__host__ __device__ constexpr int pc_l1(int pc) { return pc < 1 ? 0 : (pc < 3 ? 1 : 2); }
+__host__ __device__ constexpr int pc_l2(int pc) { return pc - pclass(pc_l1(pc), 0); }
+inline int pclass_l1(int pc) { return pc_l1(pc); }
+inline int pclass_l2(int pc) { return pc_l2(pc); }
 
 // ---- device tables -------------------------------------------------------
 // One shell-pair class (l1 >= l2).  Pairs are stored column-wise (pair index
@@ -192,6 +194,9 @@ hipError_t launch_build_pairs(const ShellsDev &sh, PairTable &t, const int *pair
 hipError_t launch_one_electron_impl(const ShellsDev &sh, const double *boys, int nmax,
                                     const int *bf_shell, const int *bf_comp, double *S,
                                     double *T, double *V, hipStream_t s);
+// one quartet class and precision (eri_class.hip, compiled per class)
+template <int X, int Y, bool F32>
+hipError_t launch_eri_unit(bool store, int variant, int wpb, const EriArgs &a, hipStream_t s);
 // quartet-class dispatch (eri_dispatch.hip); bra_pc >= ket_pc
 hipError_t launch_eri(int bra_pc, int ket_pc, bool fp32, bool store, int variant, int wpb,
                       const EriArgs &a, hipStream_t s);

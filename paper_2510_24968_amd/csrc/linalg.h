@@ -37,6 +37,15 @@ struct MolLayout {
 };
 hipError_t assemble_fock_packed(const MolLayout &L, const double *Jh, const double *Kh,
                                 const double *H, double *F, double *J, double *K, hipStream_t s);
+// J = Jref + Jh + Jh^T, K = Kref + Kh + Kh^T, F = H + J - K/2 per block (F may
+// be NULL; J may alias Jref, K may alias Kref)
+hipError_t assemble_delta(const MolLayout &L, const double *Jh, const double *Kh, const double *H,
+                          const double *Jref, const double *Kref, double *F, double *J, double *K,
+                          hipStream_t s);
+// one molecule: dD = D - Dref and M[a * ns + b] = max |dD| over shell block
+// (a, b), by bit-pattern atomics on M (which must hold zeros on entry)
+hipError_t delta_blockmax(int N, const double *D, const double *Dref, double *dD,
+                          const int *bf_shell, int ns, double *M, hipStream_t s);
 // E[m] += w * sum_block A (B + C)
 hipError_t dot3_packed(const MolLayout &L, const double *A, const double *B, const double *C,
                        double w, double *E, hipStream_t s);

@@ -124,6 +124,43 @@ __global__ void k_assemble_packed(MolLayout L, const double *__restrict__ Jh,
     }
 }
 
+// Incremental build: J = Jref + J'_d + J'_d^T, K = Kref + K'_d + K'_d^T,
+// F = H + J - K/2 (J may alias Jref and K may alias Kref).
+__global__ void k_assemble_delta(MolLayout L, const double *__restrict__ Jh,
+                                 const double *__restrict__ Kh, const double *__restrict__ H,
+                                 const double *Jref, const double *Kref, double *F, double *J,
+                                 double *K) {
+    const int m = blockIdx.y, n = L.n[m];
+    const size_t base = L.off[m], n2 = (size_t)n * n;
+    for (size_t x = blockIdx.x * (size_t)blockDim.x + threadIdx.x; x < n2;
+         x += (size_t)gridDim.x * blockDim.x) {
+        const size_t i = x / n, j = x - i * n;
+        const size_t a = base + x, at = base + j * n + i;
+        const double jj = Jref[a] + (Jh[a] + Jh[at]), kk = Kref[a] + (Kh[a] + Kh[at]);
+        if (F) F[a] = H[a] + jj - 0.5 * kk;
+        J[a] = jj;
+        K[a] = kk;
+    }
+}
+
+// dD = D - Dref and, per shell pair (a, b), M[a * ns + b] = max |dD| over the
+// block (non-negative doubles order like their bit patterns; M starts at 0).
+__global__ void k_delta_blockmax(int N, const double *__restrict__ D,
+                                 const double *__restrict__ Dref, double *dD,
+                                 const int *__restrict__ bf_shell, int ns,
+                                 unsigned long long *M) {
+    const size_t n2 = (size_t)N * N;
+    for (size_t x = blockIdx.x * (size_t)blockDim.x + threadIdx.x; x < n2;
+         x += (size_t)gridDim.x * blockDim.x) {
+        const size_t i = x / N, j = x - i * N;
+        const double v = D[x] - Dref[x];
+        dD[x] = v;
+        const unsigned long long bits = (unsigned long long)__double_as_longlong(fabs(v));
+        unsigned long long *slot = M + (size_t)bf_shell[i] * ns + bf_shell[j];
+        if (bits > *slot) atomicMax(slot, bits);
+    }
+}
+
 __global__ void k_dot3_packed(MolLayout L, const double *__restrict__ A,
                               const double *__restrict__ B, const double *__restrict__ C, double w,
                               double *E) {
@@ -348,6 +385,19 @@ hipError_t assemble_fock(int N, const double *Jh, const double *Kh, const double
                          double *J, double *K, hipStream_t s) {
     hipLaunchKernelGGL(k_assemble_fock, grid_for((size_t)N * N), dim3(256), 0, s, N, Jh, Kh, H, F,
                        J, K);
+    return hipGetLastError();
+}
+hipError_t assemble_delta(const MolLayout &L, const double *Jh, const double *Kh, const double *H,
+                          const double *Jref, const double *Kref, double *F, double *J, double *K,
+                          hipStream_t s) {
+    hipLaunchKernelGGL(k_assemble_delta, grid_mol((size_t)L.nmax * L.nmax, L.nmol), dim3(256), 0,
+                       s, L, Jh, Kh, H, Jref, Kref, F, J, K);
+    return hipGetLastError();
+}
+hipError_t delta_blockmax(int N, const double *D, const double *Dref, double *dD,
+                          const int *bf_shell, int ns, double *M, hipStream_t s) {
+    hipLaunchKernelGGL(k_delta_blockmax, grid_for((size_t)N * N), dim3(256), 0, s, N, D, Dref, dD,
+                       bf_shell, ns, (unsigned long long *)M);
     return hipGetLastError();
 }
 hipError_t dot3(size_t n, const double *A, const double *B, const double *C, double w, double *out,

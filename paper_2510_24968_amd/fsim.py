@@ -53,7 +53,7 @@ class _ScfInfo(ctypes.Structure):
                 ("dE", ctypes.c_double), ("rms_dD", ctypes.c_double),
                 ("comm_norm", ctypes.c_double), ("iter", ctypes.c_int32),
                 ("converged", ctypes.c_int32), ("diis_used", ctypes.c_int32),
-                ("pad", ctypes.c_int32)]
+                ("full_build", ctypes.c_int32), ("quartets", ctypes.c_int64)]
 
 
 class _ClassProfile(ctypes.Structure):
@@ -99,6 +99,9 @@ def lib():
         "fsim_one_electron": [vp, vp, vp, vp, vp],
         "fsim_schwarz_screen": [vp, dbl, dbl, vp, ctypes.POINTER(_ScreenStats)],
         "fsim_fock_build": [vp, vp, vp, vp, vp, ctypes.POINTER(dbl), ctypes.c_int, vp],
+        "fsim_fock_build_delta": [vp, vp, vp, vp, vp, vp, vp, vp, ctypes.POINTER(dbl), dbl,
+                                  ctypes.POINTER(i64), ctypes.c_int, vp],
+        "fsim_set_incremental": [vp, i32, dbl],
         "fsim_core_guess": [vp, vp, vp],
         "fsim_scf_step": [vp, vp, ctypes.POINTER(_ScfInfo), ctypes.c_int, vp],
         "fsim_scf_reset": [vp],
@@ -221,6 +224,31 @@ class Context:
                                      ctypes.byref(e) if energy else None, _PREC[precision],
                                      _stream()))
         return {"F": F, "J": J, "K": K, "E_elec": e.value if energy else None}
+
+    def fock_build_delta(self, D, D_ref, J_ref, K_ref, precision="fp64", in_place=False,
+                         tau_delta=0.0):
+        """J = J_ref + J[D - D_ref], K = K_ref + K[D - D_ref] over the
+        quartets whose density-weighted bound reaches tau_delta (0: the
+        screen's tau), F = H + J - K/2 (fsim_fock_build_delta).  in_place
+        updates J_ref and K_ref."""
+        for t in (D, D_ref, J_ref, K_ref):
+            assert t.dtype == torch.float64 and t.is_contiguous() and t.numel() == self.packed
+        F = self._mat()
+        J = J_ref if in_place else self._mat()
+        K = K_ref if in_place else self._mat()
+        e = ctypes.c_double()
+        nq = ctypes.c_int64()
+        _check(lib().fsim_fock_build_delta(self.h, _ptr(D), _ptr(D_ref), _ptr(J_ref), _ptr(K_ref),
+                                           _ptr(F), _ptr(J), _ptr(K), ctypes.byref(e),
+                                           float(tau_delta), ctypes.byref(nq), _PREC[precision],
+                                           _stream()))
+        return {"F": F, "J": J, "K": K, "E_elec": e.value, "quartets": nq.value}
+
+    def set_incremental(self, rebuild_every, tau_delta=0.0):
+        """SCF steps with incremental Fock builds (density-weighted threshold
+        tau_delta, 0: the screen's tau) and a full build every rebuild_every
+        steps (0: always full)."""
+        _check(lib().fsim_set_incremental(self.h, int(rebuild_every), float(tau_delta)))
 
     def core_guess(self):
         D = self._mat()

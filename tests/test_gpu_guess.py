@@ -9,9 +9,12 @@ SCF run.
 Tolerances: the GEMM's FP32 accumulation differs from the CPU's only in
 summation order, so |C - C_ref| <= K 2^-23 (|A| |B|) elementwise; BF16
 outputs are bit-exact (both sides round the same FP32 value to nearest
-even).  Gradients against the oracle that rounds at the same points as the
-GPU: relative norm error 1e-3 (FP32 accumulation order can flip single BF16
-roundings, each worth 2^-8 relative)."""
+even).  Forward output and gradients against the oracle that rounds at the
+same points as the GPU, element by element: each element within 2^-6 of its
+magnitude scale (the same product over absolute values, |A|^T |G| for a
+weight gradient), since FP32 accumulation order can flip single BF16
+roundings (2^-8 relative each) that then propagate; and almost every element
+(all but 0.5%) within 2^-12 of it."""
 
 import ctypes
 
@@ -121,20 +124,22 @@ def test_training_kernels_against_numpy():
     d = (H.astype(np.float64) - T) * mask
     assert abs(loss.item() - (d * d).sum() * inv) < 1e-5 * (d * d).sum() * inv
     assert np.allclose(dY.cpu().numpy(), 2 * d * inv, rtol=1e-6, atol=1e-12)
-    # Adam, three steps, against the textbook update in FP64
+    # Adam, three steps, against torch.optim.Adam (an independent
+    # implementation of the same bias-corrected update) in FP64 on the CPU
     w = rng.standard_normal(1000).astype(np.float32)
     wt = torch.from_numpy(w.copy()).cuda()
     m1 = torch.zeros(1000, device="cuda")
     m2 = torch.zeros(1000, device="cuda")
     wb = torch.empty(1000, dtype=torch.int16, device="cuda")
-    wr, a1, a2 = w.astype(np.float64), np.zeros(1000), np.zeros(1000)
+    wref = torch.nn.Parameter(torch.from_numpy(w.astype(np.float64)))
+    opt = torch.optim.Adam([wref], lr=1e-2, betas=(0.9, 0.999), eps=1e-8)
     for step in range(1, 4):
         gr = rng.standard_normal(1000).astype(np.float32)
         assert L.fsim_adam(1000, g._p(wt), g._p(torch.from_numpy(gr).cuda()), g._p(m1), g._p(m2),
                            1e-2, 0.9, 0.999, 1e-8, step, g._p(wb), s) == 0
-        a1 = 0.9 * a1 + 0.1 * gr
-        a2 = 0.999 * a2 + 0.001 * gr.astype(np.float64) ** 2
-        wr = wr - 1e-2 * (a1 / (1 - 0.9 ** step)) / (np.sqrt(a2 / (1 - 0.999 ** step)) + 1e-8)
+        wref.grad = torch.from_numpy(gr.astype(np.float64))
+        opt.step()
+    wr = wref.detach().numpy()
     assert np.allclose(wt.cpu().numpy(), wr, rtol=0, atol=1e-5)
     assert torch.equal(wb.cpu(), wt.cpu().to(torch.bfloat16).view(torch.int16))
 
@@ -149,6 +154,39 @@ def _net_and_batch(n=700, seed=3):
     return net, X, T, M
 
 
+def _magnitude_scales(X, T, M, W, b):
+    """Element-wise magnitude scales of the oracle's forward output and
+    gradients: the same products taken over absolute values (|X||W| + |b|
+    through the layers; |A_k|^T |G_k| for the weight gradients with |G|
+    back-propagated through |W| under the oracle's ReLU masks)."""
+    rd = omlp.round_bf16
+    pre, acts, Y = omlp.forward(X, W, b, bf16=True)
+    h = np.abs(acts[0])
+    for k in range(3):
+        h = h @ np.abs(rd(W[k])) + np.abs(b[k])
+        if k < 2:
+            h = h * (pre[k] > 0)
+    y_scale = h
+    count = float(np.sum(M))
+    g = np.abs(2.0 * (Y - T) * M / count)
+    sW, sb = [None] * 3, [None] * 3
+    for k in (2, 1, 0):
+        sW[k] = np.abs(acts[k]).T @ g
+        sb[k] = g.sum(axis=0)
+        if k > 0:
+            g = (g @ np.abs(rd(W[k])).T) * (pre[k - 1] > 0)
+    return y_scale, sW, sb
+
+
+def _elementwise(name, got, ref, scale):
+    err = np.abs(got - ref)
+    worst = float(np.max(err / (scale + 1e-30)))
+    loose = float(np.mean(err > 2.0 ** -12 * scale + 1e-30))
+    print(f"{name}: max |err|/scale {worst:.2e}, share above 2^-12 {loose:.2e}", flush=True)
+    assert np.all(err <= 2.0 ** -6 * scale + 1e-30), name
+    assert loose <= 5e-3, name
+
+
 def test_forward_backward_against_oracle():
     g = _g()
     net, X, T, M = _net_and_batch()
@@ -157,16 +195,15 @@ def test_forward_backward_against_oracle():
     Xb = net.to_bf16(torch.from_numpy(X).cuda())
     loss, dW, db = net.gradients(Xb, torch.from_numpy(T).cuda(), torch.from_numpy(M).cuda())
     Y = net.forward(Xb)[0].cpu().double().numpy()
-    # the oracle rounding at the same points
+    # the oracle rounding at the same points, compared element by element
     l16, gW16, gb16 = omlp.loss_and_grads(X, T, M, W, b, bf16=True)
     y16 = omlp.forward(X, W, b, bf16=True)[2]
-    rel = lambda a, r: np.linalg.norm(a - r) / np.linalg.norm(r)
-    assert rel(Y, y16) < 1e-3
+    y_scale, sW, sb = _magnitude_scales(X, T, M, W, b)
+    _elementwise("forward Y", Y, y16, y_scale)
     assert abs(loss.item() - l16) < 1e-3 * l16
     for k in range(3):
-        e1, e2 = rel(dW[k].cpu().double().numpy(), gW16[k]), rel(db[k].cpu().double().numpy(), gb16[k])
-        print(f"layer {k}: dW rel {e1:.2e} db rel {e2:.2e}")
-        assert e1 < 1e-3 and e2 < 1e-3
+        _elementwise(f"layer {k} dW", dW[k].cpu().double().numpy(), gW16[k], sW[k])
+        _elementwise(f"layer {k} db", db[k].cpu().double().numpy(), gb16[k], sb[k])
     # and against exact FP64 arithmetic: BF16 costs well under a percent
     l64, gW64, _ = omlp.loss_and_grads(X, T, M, W, b)
     assert abs(loss.item() - l64) < 2e-2 * l64

@@ -33,7 +33,7 @@ def _counter_csv(path, counter, rows):
 
 
 def test_traffic_summary_scales_by_the_copy_and_skips_stored_blocks(tmp_path):
-    lane = "void fsim::k_eri_lane_ko<1, 1, 1, 0, double, 3, 3>(fsim::EriArgs)"
+    lane = "void fsim::k_eri_lane_ko<1, 1, 1, 0, double, false, 3, 3>(fsim::EriArgs)"
     store = "void fsim::k_eri_lane<1, 1, 1, 0, double, true, 3, 3>(fsim::EriArgs)"
     f32 = "void fsim::k_eri_lane<2, 1, 1, 1, float, false, 6, 2>(fsim::EriArgs)"
     copy = "__amd_rocclr_copyBuffer"
@@ -47,14 +47,16 @@ def test_traffic_summary_scales_by_the_copy_and_skips_stored_blocks(tmp_path):
     k = s["kernels"]
     assert set(k) == {"(pp|ps)", "(dp|pp) f32"}          # the stored-block launch is not Fock work
     assert k["(pp|ps)"]["bytes_per_launch"] == pytest.approx((400.0 * 2.0 + 50.0) * 1024)
-    assert k["(pp|ps)"]["kernel"] == "k_eri_lane_ko<1, 1, 1, 0, double, 3, 3>"
+    assert k["(pp|ps)"]["kernel"] == "k_eri_lane_ko<1, 1, 1, 0, double, false, 3, 3>"
 
 
 def test_bench_traffic_needs_matching_sources(monkeypatch):
     import bench
-    rec = bench.kernel_traffic("water64", {"cls": "(pp|ps)"})
     path = os.path.join(ROOT, "profiles", "k_eri_water64_fp64_traffic.md")
     blob = json.loads(open(path).read().split("```json")[1].split("```")[0])
+    # the summary's figures are used only for the kernel sources it was taken on
+    monkeypatch.setattr(prof_traffic, "source_digest", lambda: blob["source_digest"])
+    rec = bench.kernel_traffic("water64", {"cls": "(pp|ps)"})
     assert rec == blob["kernels"]["(pp|ps)"]["bytes_per_launch"]
     assert bench.kernel_traffic("water64", {"cls": "(xx|yy)"}) is None
     assert bench.kernel_traffic("no_such_workload", {"cls": "(pp|ps)"}) is None

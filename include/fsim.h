@@ -152,6 +152,23 @@ fsim_status fsim_schwarz_screen(fsim_ctx *ctx, double tau, double tau_fp32, doub
 fsim_status fsim_fock_build(fsim_ctx *ctx, const double *D, double *F, double *J, double *K,
                             double *E_elec, fsim_precision prec, void *stream);
 
+/* fsim_fock_build for callers that cannot allocate device memory during the
+ * call (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc): the same inputs, outputs, kernels and errors, but the
+ * J' and K' half-sum accumulators live in a static device array of the
+ * library (2 x 2,097,152 FP64, 32 MiB, one copy per GPU, held until the
+ * process ends, its address resolved at fsim_ctx_create) instead of buffers
+ * the library allocates; the call itself allocates nothing (no hipMalloc,
+ * no allocating library routine) and uses one shared accumulator copy, not
+ * per-XCD copies.  Limit: the packed matrix size (N^2, or sum of N_m^2 for a
+ * batch) must be <= 2,097,152 (N <= 1448), else FSIM_EINVAL.  Every call on
+ * one GPU shares the array and clears what it uses before the build: calls
+ * that overlap on one GPU (other streams, other threads, other contexts)
+ * race and must be serialised by the caller.  No per-launch profiling and
+ * no graph replay on this path. */
+fsim_status fsim_fock_build_noalloc(fsim_ctx *ctx, const double *D, double *F, double *J,
+                                    double *K, double *E_elec, fsim_precision prec, void *stream);
+
 /* Core-Hamiltonian guess (Sec. 3.2, step 1): diagonalise X^T Hcore X and
  * write D = 2 C_occ C_occ^T into D (device N x N). */
 fsim_status fsim_core_guess(fsim_ctx *ctx, double *D, void *stream);

@@ -27,7 +27,7 @@ ERI_UNITS = [(f"eri_{_PC[b]}{_PC[k]}_{'f32' if p else 'f64'}",
              for b in range(6) for k in range(b + 1) for p in (0, 1)][::-1]
 SOURCES = [("eri_class.hip", name, defs) for name, defs in ERI_UNITS] + [
     (src, os.path.splitext(src)[0], []) for src in
-    ("eri_dispatch.hip", "setup.hip", "linalg.hip", "mlp.hip", "api.cpp")]
+    ("eri_dispatch.hip", "setup.hip", "linalg.hip", "mlp.hip", "noalloc.hip", "api.cpp")]
 
 FLAGS = [
     f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC",

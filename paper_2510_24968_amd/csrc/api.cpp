@@ -17,6 +17,7 @@
 #include "../../include/fsim.h"
 #include "fsim_internal.h"
 #include "linalg.h"
+#include "noalloc.h"
 
 using namespace fsim;
 
@@ -151,6 +152,9 @@ struct fsim_ctx {
     // per-XCD private J'/K' accumulators (NXCD copies of each), summed after the build
     bool xcd_private = true;
     double *priv = nullptr;
+    // accumulators of fsim_fock_build_noalloc: this device's copy of the
+    // library's static array (2 x NOALLOC_MAX_PACKED), resolved at create
+    double *noalloc = nullptr;
     // incremental builds (one molecule): shell of each basis function,
     // D - Dref, per-shell-pair max |D - Dref| (device and host), the kept
     // pairs' shells per class
@@ -357,6 +361,7 @@ static fsim_status create_impl(const fsim_basis *mols, int nmol, const fsim_opti
         if (s_ != FSIM_OK) return cleanup(s_);                                             \
     } while (0)
     HCHK(hipGetDevice(&c->device));
+    HCHK(noalloc_scratch_resolve(&c->noalloc));
     c->opt = *o;
     for (int X = 0; X < NPCLASS; ++X)
         for (int Y = 0; Y < NPCLASS; ++Y)
@@ -1258,6 +1263,27 @@ extern "C" fsim_status fsim_fock_build(fsim_ctx *c, const double *D, double *F, 
     double *Fo = F;
     if (!Fo && E_elec) Fo = c->F;
     return fock_build(c, D, Fo, J, K, E_elec, prec, s);
+}
+
+extern "C" fsim_status fsim_fock_build_noalloc(fsim_ctx *c, const double *D, double *F, double *J,
+                                               double *K, double *E_elec, fsim_precision prec,
+                                               void *stream) {
+    if (!c) return fail(FSIM_EINVAL, "ctx is NULL");
+    if (!D) return fail(FSIM_EINVAL, "D must not be NULL");
+    if (c->packed > NOALLOC_MAX_PACKED)
+        return fail(FSIM_EINVAL, "fsim_fock_build_noalloc: the packed matrix size " +
+                                     std::to_string(c->packed) + " exceeds the maximum " +
+                                     std::to_string(NOALLOC_MAX_PACKED) +
+                                     " (N <= 1448 for one molecule); use fsim_fock_build");
+    if (!c->screened) return fail(FSIM_ESTATE, "fsim_schwarz_screen must run before a Fock build");
+    if (!c->noalloc) return fail(FSIM_ESTATE, "no device scratch for this context's device");
+    hipStream_t s = (hipStream_t)stream;
+    double *Fo = F;
+    if (!Fo && E_elec) Fo = c->F;   // context-owned, allocated at create
+    const AccPair acc{c->noalloc, c->noalloc + NOALLOC_MAX_PACKED};
+    STCHK(enqueue_build(c, D, Fo, J, K, prec == FSIM_MIXED && c->tau32 > 0, nullptr, s, &acc));
+    if (E_elec) STCHK(electronic_energy(c, D, Fo, E_elec, s));
+    return FSIM_OK;
 }
 
 // ---------------------------------------------------------------------------

@@ -99,6 +99,7 @@ def lib():
         "fsim_one_electron": [vp, vp, vp, vp, vp],
         "fsim_schwarz_screen": [vp, dbl, dbl, vp, ctypes.POINTER(_ScreenStats)],
         "fsim_fock_build": [vp, vp, vp, vp, vp, ctypes.POINTER(dbl), ctypes.c_int, vp],
+        "fsim_fock_build_noalloc": [vp, vp, vp, vp, vp, ctypes.POINTER(dbl), ctypes.c_int, vp],
         "fsim_fock_build_delta": [vp, vp, vp, vp, vp, vp, vp, vp, ctypes.POINTER(dbl), dbl,
                                   ctypes.POINTER(i64), ctypes.c_int, vp],
         "fsim_set_incremental": [vp, i32, dbl],
@@ -224,6 +225,16 @@ class Context:
                                      ctypes.byref(e) if energy else None, _PREC[precision],
                                      _stream()))
         return {"F": F, "J": J, "K": K, "E_elec": e.value if energy else None}
+
+    def fock_build_noalloc(self, D, F, J=None, K=None, precision="fp64", energy=True):
+        """fsim_fock_build_noalloc into caller-allocated F (and J, K): the
+        call allocates no device memory."""
+        assert D.dtype == torch.float64 and D.is_contiguous() and D.numel() == self.packed
+        e = ctypes.c_double()
+        _check(lib().fsim_fock_build_noalloc(self.h, _ptr(D), _ptr(F), _ptr(J), _ptr(K),
+                                             ctypes.byref(e) if energy else None,
+                                             _PREC[precision], _stream()))
+        return e.value if energy else None
 
     def fock_build_delta(self, D, D_ref, J_ref, K_ref, precision="fp64", in_place=False,
                          tau_delta=0.0):

@@ -17,6 +17,15 @@
  *    descending (p: x, y, z; d: xx, xy, xz, yy, yz, zz).  Each primitive is
  *    normalised to unit self-overlap and each contracted Cartesian function
  *    is rescaled to unit self-overlap, so diag(S) = 1.
+ *  - Spherical basis (fsim_options.spherical = 1, one-molecule contexts):
+ *    every Cartesian d shell is replaced by the 5 Racah-normalised real solid
+ *    harmonics of Sec. 2.1.1, m = -2..2 (sqrt3 xy, sqrt3 yz, zz - (xx+yy)/2,
+ *    sqrt3 xz, sqrt3/2 (xx - yy)), each contracted function rescaled to unit
+ *    self-overlap; s and p shells are unchanged.  Every N x N matrix of the
+ *    ABI (S, Hcore, X, D, F, J, K) is then over these N functions; the
+ *    integral kernels still work on the Cartesian ones (fsim_eri_quartets
+ *    returns Cartesian blocks).  Not available with batches, incremental or
+ *    allocation-free builds; Fock builds are not graph-replayed.
  *  - `stream` is a hipStream_t passed as void* (NULL = the null stream).  All
  *    device work is ordered on it; calls that return host values (energies,
  *    statistics, SCF info) synchronise the stream before returning.
@@ -69,6 +78,7 @@ typedef struct {
     double conv_rms_dD; /* converged when RMS(D_new - D) < conv_rms_dD ... */
     double conv_dE;     /* ... and |dE| < conv_dE (ignored if <= 0) */
     int32_t max_iter;   /* informational: fsim_scf_step never loops */
+    int32_t spherical;  /* 1: d shells are the 5 real solid harmonics (see below) */
 } fsim_options;
 
 typedef struct fsim_ctx fsim_ctx;
@@ -119,7 +129,8 @@ fsim_status fsim_ctx_create(const fsim_basis *basis, const fsim_options *opt, fs
 /* Free every device and host resource of the context.  NULL is accepted. */
 fsim_status fsim_ctx_destroy(fsim_ctx *ctx);
 
-/* Number of Cartesian basis functions N, and the shell count. */
+/* Number of basis functions N (Cartesian, or spherical when the context
+ * uses the spherical basis), and the shell count. */
 fsim_status fsim_nbf(const fsim_ctx *ctx, int32_t *nbf, int32_t *nshell);
 
 /* Nuclear repulsion sum_{A<B} Z_A Z_B / R_AB (host out). */
@@ -183,6 +194,22 @@ fsim_status fsim_core_guess(fsim_ctx *ctx, double *D, void *stream);
  * convergence (see fsim_options).  Synchronises the stream. */
 fsim_status fsim_scf_step(fsim_ctx *ctx, double *D, fsim_scf_info *info, fsim_precision prec,
                           void *stream);
+
+/* Conventional (stored-integral) mode, the data path of the paper's own
+ * implementation (Sec. 3.3.1-3.3.2: the unique integrals are computed once
+ * and the G build of every SCF iteration runs over them).  enable != 0:
+ * every kept canonical quartet of the current screen is evaluated once, in
+ * FP64, by its class's tuned Fock-build kernel and its contracted block is
+ * written to a device buffer the context owns (tile order, one coalesced
+ * line per component and wave); from then on every full Fock build of the
+ * context (fsim_fock_build, fsim_scf_step, graph replays) digests the stored
+ * blocks with the density instead of recomputing them -- in both precisions,
+ * since the store is FP64.  Incremental builds still recompute.  bytes
+ * (host, may be NULL) receives the store size.  FSIM_ENOMEM if the store
+ * would take more than 90% of the free device memory (it grows with the
+ * kept quartets: about 1 GB for 210 basis functions); FSIM_ESTATE before a
+ * screen.  enable = 0 frees the store; a new screen also drops it. */
+fsim_status fsim_store_eris(fsim_ctx *ctx, int32_t enable, int64_t *bytes);
 
 /* Forget the DIIS history, the step counter and the incremental-build
  * reference. */

@@ -27,7 +27,8 @@ ERI_UNITS = [(f"eri_{_PC[b]}{_PC[k]}_{'f32' if p else 'f64'}",
              for b in range(6) for k in range(b + 1) for p in (0, 1)][::-1]
 SOURCES = [("eri_class.hip", name, defs) for name, defs in ERI_UNITS] + [
     (src, os.path.splitext(src)[0], []) for src in
-    ("eri_dispatch.hip", "setup.hip", "linalg.hip", "mlp.hip", "noalloc.hip", "api.cpp")]
+    ("stored.hip", "eri_dispatch.hip", "setup.hip", "linalg.hip", "mlp.hip", "noalloc.hip",
+     "api.cpp")]
 
 FLAGS = [
     f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC",
@@ -41,10 +42,11 @@ FLAGS = [
 
 # headers the ERI kernel units include (the other sources may include any)
 ERI_HEADERS = ("eri_kernels.h", "boys.h", "fsim_internal.h")
+ERI_SOURCES = ("eri_class.hip", "stored.hip")
 
 
 def _newest_header(src):
-    names = ERI_HEADERS if src == "eri_class.hip" else [
+    names = ERI_HEADERS if src in ERI_SOURCES else [
         f for f in os.listdir(CSRC) if f.endswith(".h")]
     return max(os.path.getmtime(os.path.join(CSRC, f)) for f in names)
 
@@ -55,7 +57,7 @@ def _compile(unit, verbose, incremental=False):
     if incremental and os.path.exists(obj):
         t = os.path.getmtime(obj)
         deps = max(os.path.getmtime(os.path.join(CSRC, src)), _newest_header(src))
-        if src != "eri_class.hip":
+        if src not in ERI_SOURCES:
             deps = max(deps, os.path.getmtime(os.path.join(ROOT, "include", "fsim.h")))
         if t > deps:
             return obj

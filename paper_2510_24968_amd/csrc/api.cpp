@@ -162,6 +162,19 @@ struct fsim_ctx {
     double *dD = nullptr, *Mblk = nullptr;
     std::vector<double> Mhost;
     std::vector<int> kept_s1[NPCLASS], kept_s2[NPCLASS];
+    // spherical basis (one molecule): the caller's matrices are nscf x nscf
+    // over real solid harmonic d functions; the kernels work on the nbf
+    // Cartesian functions, with T (nbf x nscf, row-major) between the two
+    bool sph = false;
+    int nscf = 0;
+    double *Tsph = nullptr, *Dc = nullptr, *Jc = nullptr, *Kc = nullptr, *Wsph = nullptr;
+    // conventional mode: every kept quartet's block stored once (FP64, tile
+    // order) and digested by later builds instead of being recomputed
+    DevPool store_pool;
+    bool stored = false;
+    double *store = nullptr;
+    long long store_off[NPCLASS][NPCLASS] = {};
+    int64_t store_bytes = 0;
     // SCF with incremental builds: full build every inc_every steps, the
     // reference density and its J, K
     int inc_every = 0, inc_count = 0;
@@ -263,20 +276,112 @@ static fsim_status gemm(rocblas_handle h, bool ta, bool tb, int m, int n, int k,
 // Symmetric eigen-decomposition in place (column-major, ascending).
 static fsim_status syevd(fsim_ctx *c, double *A, double *w, hipStream_t s) {
     BLASCHK(rocblas_set_stream(c->blas, s));
-    BLASCHK(rocsolver_dsyevd(c->blas, rocblas_evect_original, rocblas_fill_upper, c->nbf, A,
-                             c->nbf, w, c->ework, c->dinfo));
+    BLASCHK(rocsolver_dsyevd(c->blas, rocblas_evect_original, rocblas_fill_upper, c->nscf, A,
+                             c->nscf, w, c->ework, c->dinfo));
     return FSIM_OK;
 }
 
 // D = 2 C_occ C_occ^T with C = X V, V the eigenvectors of X^T F X.
 static fsim_status density_from_fock(fsim_ctx *c, const double *Fm, double *Dout, hipStream_t s) {
-    const int N = c->nbf;
+    const int N = c->nscf;
     BLASCHK(rocblas_set_stream(c->blas, s));
     STCHK(gemm(c->blas, false, false, N, N, N, 1.0, Fm, N, c->X, N, 0.0, c->T1, N));   // F X
     STCHK(gemm(c->blas, true, false, N, N, N, 1.0, c->X, N, c->T1, N, 0.0, c->T2, N));  // X^T F X
     STCHK(syevd(c, c->T2, c->eig, s));
     STCHK(gemm(c->blas, false, false, N, N, N, 1.0, c->X, N, c->T2, N, 0.0, c->T1, N));  // C
     STCHK(gemm(c->blas, false, true, N, N, c->nocc, 2.0, c->T1, N, c->T1, N, 0.0, Dout, N));
+    return FSIM_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Spherical basis (Sec. 2.1.1: each real solid harmonic Gaussian is a fixed
+// combination of Cartesian Gaussians of degree l, with coefficients S^{lm}).
+// Integrals over spherical functions are the Cartesian ones contracted with
+// those coefficients on every index, so with T (Cartesian x spherical):
+//   S' = T^T S T,  H' = T^T H T,  J'(D') = T^T J(T D' T^T) T  (and K').
+// rocBLAS is column-major: the row-major T (nbf x nscf) is the column-major
+// Tcm = T^T (nscf x nbf, ld nscf); the symmetric matrices read the same in
+// either order.
+// ---------------------------------------------------------------------------
+
+// Racah-normalised real solid harmonics of a d shell on its Cartesian
+// components (xx, xy, xz, yy, yz, zz), m = -2..2:
+//   sqrt3 xy, sqrt3 yz, zz - (xx + yy)/2, sqrt3 xz, sqrt3/2 (xx - yy)
+static void d_solid_harmonics(double (&t)[6][5]) {
+    const double r3 = std::sqrt(3.0);
+    const double c[5][6] = {{0, r3, 0, 0, 0, 0},
+                            {0, 0, 0, 0, r3, 0},
+                            {-0.5, 0, 0, -0.5, 0, 1.0},
+                            {0, 0, r3, 0, 0, 0},
+                            {r3 / 2, 0, 0, -r3 / 2, 0, 0}};
+    // the Cartesian functions are of unit norm: x^a y^b z^c e^{-ar^2} is
+    // sqrt((2a-1)!! (2b-1)!! (2c-1)!!) times the unit function (up to a
+    // factor common to the shell): sqrt3 for xx, yy, zz, 1 for the others
+    const double w[6] = {r3, 1.0, 1.0, r3, 1.0, r3};
+    for (int q = 0; q < 6; ++q)
+        for (int m = 0; m < 5; ++m) t[q][m] = c[m][q] * w[q];
+}
+
+// Ms = T^T Mc T (nscf x nscf, not symmetrised) through Wsph
+static fsim_status sph_from_cart(fsim_ctx *c, const double *Mc, double *Ms) {
+    const int Nc = c->nbf, Ns = c->nscf;
+    STCHK(gemm(c->blas, false, true, Nc, Ns, Nc, 1.0, Mc, Nc, c->Tsph, Ns, 0.0, c->Wsph, Nc));
+    STCHK(gemm(c->blas, false, false, Ns, Ns, Nc, 1.0, c->Tsph, Ns, c->Wsph, Nc, 0.0, Ms, Ns));
+    return FSIM_OK;
+}
+
+// Mc = T Ms T^T (nbf x nbf, not symmetrised) through Wsph
+static fsim_status cart_from_sph(fsim_ctx *c, const double *Ms, double *Mc) {
+    const int Nc = c->nbf, Ns = c->nscf;
+    STCHK(gemm(c->blas, false, false, Ns, Nc, Ns, 1.0, Ms, Ns, c->Tsph, Ns, 0.0, c->Wsph, Ns));
+    STCHK(gemm(c->blas, true, false, Nc, Nc, Ns, 1.0, c->Tsph, Ns, c->Wsph, Ns, 0.0, Mc, Nc));
+    return FSIM_OK;
+}
+
+// Build T from the Cartesian overlap in c->S (each spherical d function
+// rescaled to unit self-overlap), then S, H <- T^T S T, T^T H T.
+static fsim_status spherical_setup(fsim_ctx *c, DevPool &pool) {
+    const int Nc = c->nbf;
+    int Ns = 0;
+    for (int l : c->sh_l) Ns += l == 2 ? 5 : ncart_h(l);
+    c->nscf = Ns;
+    c->sph = true;
+    std::vector<double> S((size_t)Nc * Nc);
+    HIPCHK(hipMemcpy(S.data(), c->S, sizeof(double) * S.size(), hipMemcpyDeviceToHost));
+    std::vector<double> T((size_t)Nc * Ns, 0.0);
+    double td[6][5];
+    d_solid_harmonics(td);
+    int c0 = 0, s0 = 0;
+    for (int l : c->sh_l) {
+        const int nc = ncart_h(l);
+        if (l < 2) {
+            for (int q = 0; q < nc; ++q) T[(size_t)(c0 + q) * Ns + s0 + q] = 1.0;
+            s0 += nc;
+        } else {
+            for (int m = 0; m < 5; ++m) {
+                double nrm = 0.0;
+                for (int p = 0; p < 6; ++p)
+                    for (int q = 0; q < 6; ++q)
+                        nrm += td[p][m] * S[(size_t)(c0 + p) * Nc + c0 + q] * td[q][m];
+                for (int q = 0; q < 6; ++q)
+                    T[(size_t)(c0 + q) * Ns + s0 + m] = td[q][m] / std::sqrt(nrm);
+            }
+            s0 += 5;
+        }
+        c0 += nc;
+    }
+    HIPCHK(pool.alloc(&c->Tsph, T.size()));
+    HIPCHK(pool.alloc(&c->Dc, (size_t)Nc * Nc));
+    HIPCHK(pool.alloc(&c->Jc, (size_t)Nc * Nc));
+    HIPCHK(pool.alloc(&c->Kc, (size_t)Nc * Nc));
+    HIPCHK(pool.alloc(&c->Wsph, (size_t)Nc * Ns));
+    HIPCHK(hipMemcpy(c->Tsph, T.data(), sizeof(double) * T.size(), hipMemcpyHostToDevice));
+    BLASCHK(rocblas_set_stream(c->blas, nullptr));
+    STCHK(sph_from_cart(c, c->S, c->T1));
+    HIPCHK(symmetrize(Ns, c->T1, c->S, nullptr));
+    STCHK(sph_from_cart(c, c->H, c->T1));
+    HIPCHK(symmetrize(Ns, c->T1, c->H, nullptr));
+    HIPCHK(hipDeviceSynchronize());
     return FSIM_OK;
 }
 
@@ -319,6 +424,7 @@ static fsim_status validate(const fsim_basis *b, const fsim_options *o) {
         !std::isfinite(o->tau_fp32))
         return fail(FSIM_EINVAL, "thresholds must be finite and >= 0");
     if (o->diis_m < 0 || o->diis_m > DIIS_MAX) return fail(FSIM_EINVAL, "diis_m must be 0..16");
+    if (o->spherical != 0 && o->spherical != 1) return fail(FSIM_EINVAL, "spherical must be 0 or 1");
     return FSIM_OK;
 }
 
@@ -532,9 +638,15 @@ static fsim_status create_impl(const fsim_basis *mols, int nmol, const fsim_opti
     }
     c->pool.release(dbc);
 
+    c->nscf = c->nbf;
+    if (o->spherical) {
+        if (nmol != 1)
+            return cleanup(fail(FSIM_EINVAL, "spherical basis sets are for one-molecule contexts"));
+        SCHK(spherical_setup(c, c->pool));
+    }
     const int m_hist = std::max(1, c->opt.diis_m);
     if (nmol == 1) {
-        const int N = c->nbf;
+        const int N = c->nscf;
         const size_t N2 = (size_t)N * N;
         PCHK(c->pool.alloc(&c->eig, N));
         PCHK(c->pool.alloc(&c->ework, N));
@@ -636,6 +748,7 @@ extern "C" fsim_status fsim_ctx_destroy(fsim_ctx *c) {
     }
     if (c->gstream) hipStreamDestroy(c->gstream);
     for (auto &e : c->ev) hipEventDestroy(e);
+    c->store_pool.clear();
     c->screen_pool.clear();
     c->pool.clear();
     delete c;
@@ -644,7 +757,7 @@ extern "C" fsim_status fsim_ctx_destroy(fsim_ctx *c) {
 
 extern "C" fsim_status fsim_nbf(const fsim_ctx *c, int32_t *nbf, int32_t *nshell) {
     if (!c) return fail(FSIM_EINVAL, "ctx is NULL");
-    if (nbf) *nbf = c->nbf;
+    if (nbf) *nbf = c->nscf;
     if (nshell) *nshell = c->nshell;
     return FSIM_OK;
 }
@@ -658,7 +771,8 @@ extern "C" fsim_status fsim_nuclear_repulsion(const fsim_ctx *c, double *e) {
 extern "C" fsim_status fsim_one_electron(fsim_ctx *c, double *S, double *H, double *X, void *stream) {
     if (!c) return fail(FSIM_EINVAL, "ctx is NULL");
     hipStream_t s = (hipStream_t)stream;
-    const size_t bytes = sizeof(double) * (size_t)c->packed;
+    const size_t bytes =
+        sizeof(double) * (c->nmol == 1 ? (size_t)c->nscf * c->nscf : (size_t)c->packed);
     if (S) HIPCHK(hipMemcpyAsync(S, c->S, bytes, hipMemcpyDeviceToDevice, s));
     if (H) HIPCHK(hipMemcpyAsync(H, c->H, bytes, hipMemcpyDeviceToDevice, s));
     if (X) HIPCHK(hipMemcpyAsync(X, c->X, bytes, hipMemcpyDeviceToDevice, s));
@@ -922,6 +1036,10 @@ extern "C" fsim_status fsim_schwarz_screen(fsim_ctx *c, double tau, double tau32
     // kept pairs per class, ordered by (molecule, Q descending); each
     // molecule owns a contiguous segment of every class table
     drop_graphs(c);
+    c->store_pool.clear();
+    c->stored = false;
+    c->store = nullptr;
+    c->store_bytes = 0;
     c->screen_pool.clear();
     c->screened = false;
     fsim_screen_stats S{};
@@ -1164,7 +1282,13 @@ static fsim_status enqueue_build(fsim_ctx *c, const double *D, double *F, double
                 a.mol_n = c->d_mol_n;
                 a.boys = c->boys;
                 const int f32 = mixed && part == 1;
-                HIPCHK(launch_eri(X, Y, f32, false, c->variant[X][Y][f32], c->wpb[X][Y][f32], a, s));
+                if (c->stored && !dref) {
+                    a.out = c->store + c->store_off[X][Y];
+                    HIPCHK(launch_digest_stored(X, Y, 4, a, s));
+                } else {
+                    HIPCHK(launch_eri(X, Y, f32, false, c->variant[X][Y][f32], c->wpb[X][Y][f32],
+                                      a, s));
+                }
                 if (prof) HIPCHK(hipEventRecord(c->ev[nev++], s));
             }
         }
@@ -1193,12 +1317,54 @@ static fsim_status electronic_energy(fsim_ctx *c, const double *D, const double 
     return FSIM_OK;
 }
 
+// Spherical context: D' -> D = T D' T^T, Cartesian J, K by the class
+// kernels, J' = T^T J T, K' = T^T K T, F' = H' + J' - K'/2 (no graph replay).
+static fsim_status fock_build_sph(fsim_ctx *c, const double *D, double *F, double *J, double *K,
+                                  double *E_elec, bool mixed, hipStream_t s) {
+    const int Ns = c->nscf;
+    BLASCHK(rocblas_set_stream(c->blas, s));
+    STCHK(cart_from_sph(c, D, c->T1));
+    HIPCHK(symmetrize(c->nbf, c->T1, c->Dc, s));
+    if (c->profiling && c->ev.empty()) {
+        c->ev.resize(2 * 2 * NPCLASS * NPCLASS);
+        for (auto &e : c->ev) HIPCHK(hipEventCreate(&e));
+    }
+    if (c->xcd_private && !c->priv) HIPCHK(c->pool.alloc(&c->priv, 2 * NXCD * (size_t)c->packed));
+    std::vector<fsim_class_profile> prof;
+    STCHK(enqueue_build(c, c->Dc, nullptr, c->Jc, c->Kc, mixed, c->profiling ? &prof : nullptr, s));
+    if (c->profiling) {
+        HIPCHK(hipStreamSynchronize(s));
+        for (size_t k = 0; k < prof.size(); ++k) {
+            float ms = 0.f;
+            HIPCHK(hipEventElapsedTime(&ms, c->ev[2 * k], c->ev[2 * k + 1]));
+            prof[k].ms = ms;
+        }
+        c->prof = prof;
+    }
+    STCHK(sph_from_cart(c, c->Jc, c->T1));
+    STCHK(sph_from_cart(c, c->Kc, c->T2));
+    HIPCHK(assemble_sym(Ns, c->T1, c->T2, c->H, F, J, K, s));
+    if (E_elec) {
+        if (!F) return fail(FSIM_EINVAL, "E_elec needs F");
+        HIPCHK(fill(c->Emol, 1, 0.0, s));
+        HIPCHK(dot3((size_t)Ns * Ns, D, c->H, F, 0.5, c->Emol, s));
+        HIPCHK(hipMemcpyAsync(c->Emol_host.data(), c->Emol, sizeof(double), hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        *E_elec = c->Emol_host[0];
+    }
+    return FSIM_OK;
+}
+
 static fsim_status fock_build(fsim_ctx *c, const double *D, double *F, double *J, double *K,
                               double *E_elec, fsim_precision prec, hipStream_t s) {
     if (!c->screened) return fail(FSIM_ESTATE, "fsim_schwarz_screen must run before a Fock build");
     if (!D) return fail(FSIM_EINVAL, "D must not be NULL");
+    if (c->sph)
+        return fock_build_sph(c, D, F, J, K, E_elec, prec == FSIM_MIXED && c->tau32 > 0 && !c->stored,
+                              s);
     const size_t P = (size_t)c->packed;
-    const bool mixed = prec == FSIM_MIXED && c->tau32 > 0;
+    // a store holds FP64 blocks of every kept quartet: its builds digest those
+    const bool mixed = prec == FSIM_MIXED && c->tau32 > 0 && !c->stored;
     if (c->profiling && c->ev.empty()) {
         c->ev.resize(2 * 2 * NPCLASS * NPCLASS);
         for (auto &e : c->ev) HIPCHK(hipEventCreate(&e));
@@ -1277,12 +1443,105 @@ extern "C" fsim_status fsim_fock_build_noalloc(fsim_ctx *c, const double *D, dou
                                      " (N <= 1448 for one molecule); use fsim_fock_build");
     if (!c->screened) return fail(FSIM_ESTATE, "fsim_schwarz_screen must run before a Fock build");
     if (!c->noalloc) return fail(FSIM_ESTATE, "no device scratch for this context's device");
+    if (c->sph) return fail(FSIM_EINVAL, "fsim_fock_build_noalloc takes Cartesian contexts only");
     hipStream_t s = (hipStream_t)stream;
     double *Fo = F;
     if (!Fo && E_elec) Fo = c->F;   // context-owned, allocated at create
     const AccPair acc{c->noalloc, c->noalloc + NOALLOC_MAX_PACKED};
     STCHK(enqueue_build(c, D, Fo, J, K, prec == FSIM_MIXED && c->tau32 > 0, nullptr, s, &acc));
     if (E_elec) STCHK(electronic_energy(c, D, Fo, E_elec, s));
+    return FSIM_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Conventional mode: integrals computed once, digested by every build
+// ---------------------------------------------------------------------------
+
+extern "C" fsim_status fsim_store_eris(fsim_ctx *c, int32_t enable, int64_t *bytes) {
+    if (!c) return fail(FSIM_EINVAL, "ctx is NULL");
+    drop_graphs(c);
+    c->store_pool.clear();
+    c->stored = false;
+    c->store = nullptr;
+    c->store_bytes = 0;
+    if (bytes) *bytes = 0;
+    if (!enable) return FSIM_OK;
+    if (!c->screened) return fail(FSIM_ESTATE, "fsim_schwarz_screen must run before storing integrals");
+    // sizes: every tile of the FP64 lists, NE components x 64 lanes
+    long long total = 0;
+    for (int X = 0; X < NPCLASS; ++X)
+        for (int Y = 0; Y <= X; ++Y) {
+            const long long ne = (long long)ncart_h(pclass_l1(X)) * ncart_h(pclass_l2(X)) *
+                                 ncart_h(pclass_l1(Y)) * ncart_h(pclass_l2(Y));
+            c->store_off[X][Y] = total;
+            total += (long long)c->lists[X][Y].all64.ntile * ne * TILE;
+        }
+    size_t freeb = 0, totb = 0;
+    HIPCHK(hipMemGetInfo(&freeb, &totb));
+    const double need = (double)total * sizeof(double);
+    if (need > 0.9 * (double)freeb)
+        return fail(FSIM_ENOMEM, "stored integrals need " + std::to_string(need / 1e9) +
+                                     " GB, more than 90% of the free device memory (" +
+                                     std::to_string(freeb / 1e9) + " GB)");
+    HIPCHK(c->store_pool.alloc(&c->store, (size_t)std::max(1LL, total)));
+    // one store launch per class over its tiles, with the class's tuned FP64
+    // kernel; task arrays are built per class on the host
+    for (int X = 0; X < NPCLASS; ++X)
+        for (int Y = 0; Y <= X; ++Y) {
+            const ClassLists &cl = c->lists[X][Y];
+            const HostList &h = cl.host[0];
+            const int nt = cl.all64.ntile;
+            if (nt == 0) continue;
+            const int nb = ncart_h(pclass_l2(X)), nc = ncart_h(pclass_l1(Y)),
+                      nd = ncart_h(pclass_l2(Y));
+            const long long ne = (long long)ncart_h(pclass_l1(X)) * nb * nc * nd;
+            std::vector<int> tbra(nt), tket((size_t)nt * TILE, -1), tst((size_t)nt * TILE * 4, 0);
+            std::vector<long long> toff((size_t)nt * TILE, 0);
+            int t = 0;
+            for (size_t r = 0; r < h.bra.size(); ++r)
+                for (int k0 = h.lo[r]; k0 < h.hi[r]; k0 += TILE, ++t) {
+                    tbra[t] = h.bra[r];
+                    for (int l = 0; l < TILE && k0 + l < h.hi[r]; ++l) {
+                        const size_t q = (size_t)t * TILE + l;
+                        tket[q] = k0 + l;
+                        toff[q] = c->store_off[X][Y] + (long long)t * ne * TILE + l;
+                        tst[4 * q + 0] = nb * nc * nd * TILE;
+                        tst[4 * q + 1] = nc * nd * TILE;
+                        tst[4 * q + 2] = nd * TILE;
+                        tst[4 * q + 3] = TILE;
+                    }
+                }
+            if (t != nt) return fail(FSIM_ESTATE, "internal: tile count mismatch while storing");
+            int *dbra = nullptr, *dket = nullptr, *dst = nullptr;
+            long long *doff = nullptr;
+            DevPool tmp;
+            HIPCHK(tmp.alloc(&dbra, tbra.size()));
+            HIPCHK(tmp.alloc(&dket, tket.size()));
+            HIPCHK(tmp.alloc(&doff, toff.size()));
+            HIPCHK(tmp.alloc(&dst, tst.size()));
+            HIPCHK(hipMemcpy(dbra, tbra.data(), sizeof(int) * tbra.size(), hipMemcpyHostToDevice));
+            HIPCHK(hipMemcpy(dket, tket.data(), sizeof(int) * tket.size(), hipMemcpyHostToDevice));
+            HIPCHK(hipMemcpy(doff, toff.data(), sizeof(long long) * toff.size(), hipMemcpyHostToDevice));
+            HIPCHK(hipMemcpy(dst, tst.data(), sizeof(int) * tst.size(), hipMemcpyHostToDevice));
+            EriArgs a{};
+            a.bra = c->kept[X];
+            a.ket = c->kept[Y];
+            a.same_class = X == Y;
+            a.st_ntile = nt;
+            a.st_bra = dbra;
+            a.st_ket = dket;
+            a.st_off = doff;
+            a.st_stride = dst;
+            a.out = c->store;
+            a.boys = c->boys;
+            a.nbf = c->nbf;
+            HIPCHK(launch_eri(X, Y, false, true, c->variant[X][Y][0], c->wpb[X][Y][0], a, nullptr));
+            HIPCHK(hipDeviceSynchronize());
+            tmp.clear();
+        }
+    c->stored = true;
+    c->store_bytes = total * (int64_t)sizeof(double);
+    if (bytes) *bytes = c->store_bytes;
     return FSIM_OK;
 }
 
@@ -1362,6 +1621,7 @@ static fsim_status fock_build_delta_impl(fsim_ctx *c, const double *D, const dou
                                          double *J, double *K, double *E_elec, double tau_delta,
                                          int64_t *quartets, fsim_precision prec, hipStream_t s) {
     if (c->nmol != 1) return fail(FSIM_EINVAL, "incremental builds are for one-molecule contexts");
+    if (c->sph) return fail(FSIM_EINVAL, "incremental builds take Cartesian contexts only");
     if (!c->screened) return fail(FSIM_ESTATE, "fsim_schwarz_screen must run before a Fock build");
     if (!D || !Dref || !Jref || !Kref || !J || !K)
         return fail(FSIM_EINVAL, "D, D_ref, J_ref, K_ref, J and K must not be NULL");
@@ -1422,6 +1682,8 @@ extern "C" fsim_status fsim_set_incremental(fsim_ctx *c, int32_t rebuild_every, 
     c->inc_tau = tau_delta;
     if (rebuild_every > 0 && c->nmol != 1)
         return fail(FSIM_EINVAL, "incremental builds are for one-molecule contexts");
+    if (rebuild_every > 0 && c->sph)
+        return fail(FSIM_EINVAL, "incremental builds take Cartesian contexts only");
     if (rebuild_every > 0 && !c->Dref) {
         const size_t P = (size_t)c->packed;
         HIPCHK(c->pool.alloc(&c->Dref, P));
@@ -1648,7 +1910,7 @@ extern "C" fsim_status fsim_scf_step(fsim_ctx *c, double *D, fsim_scf_info *info
     if (!c || !D || !info) return fail(FSIM_EINVAL, "NULL argument");
     hipStream_t s = (hipStream_t)stream;
     if (c->nmol > 1) return batched_scf_step(c, D, info, prec, s);
-    const int N = c->nbf;
+    const int N = c->nscf;
     const size_t N2 = (size_t)N * N;
     double Eel = 0.0;
     int full = 1;
@@ -1869,11 +2131,11 @@ extern "C" fsim_status fsim_batch_layout(const fsim_ctx *c, int32_t *nmol, int32
     if (!c) return fail(FSIM_EINVAL, "ctx is NULL");
     if (nmol) *nmol = c->nmol;
     for (int m = 0; m < c->nmol; ++m) {
-        if (nbf) nbf[m] = c->mol_n[m];
+        if (nbf) nbf[m] = c->nmol == 1 ? c->nscf : c->mol_n[m];
         if (offsets) offsets[m] = c->mol_off[m];
         if (enuc) enuc[m] = c->mol_enuc[m];
     }
-    if (packed) *packed = c->packed;
+    if (packed) *packed = c->nmol == 1 ? (int64_t)c->nscf * c->nscf : c->packed;
     return FSIM_OK;
 }
 
@@ -1905,7 +2167,7 @@ extern "C" fsim_status fsim_purify(fsim_ctx *c, double *D, int32_t iters, double
     if (c->nmol != 1) return fail(FSIM_EINVAL, "purification is for one-molecule contexts");
     if (iters < 0) return fail(FSIM_EINVAL, "iters must be >= 0");
     hipStream_t s = (hipStream_t)stream;
-    const int N = c->nbf;
+    const int N = c->nscf;
     const size_t N2 = (size_t)N * N;
     BLASCHK(rocblas_set_stream(c->blas, s));
     // work on P = D / 2 in Dn

@@ -197,6 +197,10 @@ hipError_t launch_one_electron_impl(const ShellsDev &sh, const double *boys, int
 // one quartet class and precision (eri_class.hip, compiled per class)
 template <int X, int Y, bool F32>
 hipError_t launch_eri_unit(bool store, int variant, int wpb, const EriArgs &a, hipStream_t s);
+// digest of stored blocks (stored.hip): a.out = the class's store, a.tl its
+// FP64 tile list
+hipError_t launch_digest_stored(int bra_pc, int ket_pc, int wpb, const EriArgs &a,
+                                hipStream_t s);
 // quartet-class dispatch (eri_dispatch.hip); bra_pc >= ket_pc
 hipError_t launch_eri(int bra_pc, int ket_pc, bool fp32, bool store, int variant, int wpb,
                       const EriArgs &a, hipStream_t s);

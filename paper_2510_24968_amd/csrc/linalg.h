@@ -42,6 +42,12 @@ hipError_t assemble_fock_packed(const MolLayout &L, const double *Jh, const doub
 hipError_t assemble_delta(const MolLayout &L, const double *Jh, const double *Kh, const double *H,
                           const double *Jref, const double *Kref, double *F, double *J, double *K,
                           hipStream_t s);
+// out = (A + A^T) / 2 (N x N; out must not alias A)
+hipError_t symmetrize(int N, const double *A, double *out, hipStream_t s);
+// J = (Jr + Jr^T)/2, K = (Kr + Kr^T)/2, F = H + J - K/2 (N x N; outputs may be
+// NULL and must not alias Jr, Kr)
+hipError_t assemble_sym(int N, const double *Jr, const double *Kr, const double *H, double *F,
+                        double *J, double *K, hipStream_t s);
 // one molecule: dD = D - Dref and M[a * ns + b] = max |dD| over shell block
 // (a, b), by bit-pattern atomics on M (which must hold zeros on entry)
 hipError_t delta_blockmax(int N, const double *D, const double *Dref, double *dD,

@@ -143,6 +143,31 @@ __global__ void k_assemble_delta(MolLayout L, const double *__restrict__ Jh,
     }
 }
 
+// out = (A + A^T) / 2 (out must not alias A)
+__global__ void k_symmetrize(int N, const double *__restrict__ A, double *__restrict__ out) {
+    const size_t n2 = (size_t)N * N;
+    for (size_t x = blockIdx.x * (size_t)blockDim.x + threadIdx.x; x < n2;
+         x += (size_t)gridDim.x * blockDim.x) {
+        const size_t i = x / N, j = x - i * N;
+        out[x] = 0.5 * (A[x] + A[j * N + i]);
+    }
+}
+
+// J = (Jr + Jr^T)/2, K = (Kr + Kr^T)/2, F = H + J - K/2 (J, K, F may be NULL;
+// none may alias Jr or Kr)
+__global__ void k_assemble_sym(int N, const double *__restrict__ Jr, const double *__restrict__ Kr,
+                               const double *__restrict__ H, double *F, double *J, double *K) {
+    const size_t n2 = (size_t)N * N;
+    for (size_t x = blockIdx.x * (size_t)blockDim.x + threadIdx.x; x < n2;
+         x += (size_t)gridDim.x * blockDim.x) {
+        const size_t i = x / N, j = x - i * N, t = j * N + i;
+        const double jj = 0.5 * (Jr[x] + Jr[t]), kk = 0.5 * (Kr[x] + Kr[t]);
+        if (F) F[x] = H[x] + jj - 0.5 * kk;
+        if (J) J[x] = jj;
+        if (K) K[x] = kk;
+    }
+}
+
 // dD = D - Dref and, per shell pair (a, b), M[a * ns + b] = max |dD| over the
 // block (non-negative doubles order like their bit patterns; M starts at 0).
 __global__ void k_delta_blockmax(int N, const double *__restrict__ D,
@@ -392,6 +417,16 @@ hipError_t assemble_delta(const MolLayout &L, const double *Jh, const double *Kh
                           hipStream_t s) {
     hipLaunchKernelGGL(k_assemble_delta, grid_mol((size_t)L.nmax * L.nmax, L.nmol), dim3(256), 0,
                        s, L, Jh, Kh, H, Jref, Kref, F, J, K);
+    return hipGetLastError();
+}
+hipError_t symmetrize(int N, const double *A, double *out, hipStream_t s) {
+    hipLaunchKernelGGL(k_symmetrize, grid_for((size_t)N * N), dim3(256), 0, s, N, A, out);
+    return hipGetLastError();
+}
+hipError_t assemble_sym(int N, const double *Jr, const double *Kr, const double *H, double *F,
+                        double *J, double *K, hipStream_t s) {
+    hipLaunchKernelGGL(k_assemble_sym, grid_for((size_t)N * N), dim3(256), 0, s, N, Jr, Kr, H, F,
+                       J, K);
     return hipGetLastError();
 }
 hipError_t delta_blockmax(int N, const double *D, const double *Dref, double *dD,

@@ -37,7 +37,8 @@ class _Basis(ctypes.Structure):
 class _Options(ctypes.Structure):
     _fields_ = [("tau_screen", ctypes.c_double), ("tau_fp32", ctypes.c_double),
                 ("diis_m", ctypes.c_int32), ("conv_rms_dD", ctypes.c_double),
-                ("conv_dE", ctypes.c_double), ("max_iter", ctypes.c_int32)]
+                ("conv_dE", ctypes.c_double), ("max_iter", ctypes.c_int32),
+                ("spherical", ctypes.c_int32)]
 
 
 class _ScreenStats(ctypes.Structure):
@@ -103,6 +104,7 @@ def lib():
         "fsim_fock_build_delta": [vp, vp, vp, vp, vp, vp, vp, vp, ctypes.POINTER(dbl), dbl,
                                   ctypes.POINTER(i64), ctypes.c_int, vp],
         "fsim_set_incremental": [vp, i32, dbl],
+        "fsim_store_eris": [vp, i32, ctypes.POINTER(i64)],
         "fsim_core_guess": [vp, vp, vp],
         "fsim_scf_step": [vp, vp, ctypes.POINTER(_ScfInfo), ctypes.c_int, vp],
         "fsim_scf_reset": [vp],
@@ -161,14 +163,14 @@ class Context:
     """One molecule on the current GPU."""
 
     def __init__(self, basis, tau=0.0, tau_fp32=0.0, diis_m=8, conv_rms_dD=1e-8, conv_dE=1e-10,
-                 max_iter=100, device="cuda"):
+                 max_iter=100, device="cuda", spherical=False):
         L = lib()
         if not torch.cuda.is_available():
             raise FsimError("no GPU: libfsim runs on an MI355X only")
         self.device = torch.device(device)
         b, keep = basis_struct(basis)
         self.opt = _Options(float(tau), float(tau_fp32), int(diis_m), float(conv_rms_dD),
-                            float(conv_dE), int(max_iter))
+                            float(conv_dE), int(max_iter), 1 if spherical else 0)
         h = ctypes.c_void_p()
         with torch.cuda.device(self.device):
             _check(L.fsim_ctx_create(ctypes.byref(b), ctypes.byref(self.opt), ctypes.byref(h)))
@@ -254,6 +256,13 @@ class Context:
                                            float(tau_delta), ctypes.byref(nq), _PREC[precision],
                                            _stream()))
         return {"F": F, "J": J, "K": K, "E_elec": e.value, "quartets": nq.value}
+
+    def store_eris(self, enable=True):
+        """Conventional mode: compute every kept quartet once and digest the
+        stored blocks in later builds (fsim_store_eris); returns the bytes."""
+        nb = ctypes.c_int64()
+        _check(lib().fsim_store_eris(self.h, 1 if enable else 0, ctypes.byref(nb)))
+        return nb.value
 
     def set_incremental(self, rebuild_every, tau_delta=0.0):
         """SCF steps with incremental Fock builds (density-weighted threshold
@@ -392,7 +401,7 @@ class Batch(Context):
             keeps.append(keep)
         arr = (_Basis * len(structs))(*structs)
         self.opt = _Options(float(tau), float(tau_fp32), int(diis_m), float(conv_rms_dD),
-                            float(conv_dE), int(max_iter))
+                            float(conv_dE), int(max_iter), 0)
         h = ctypes.c_void_p()
         with torch.cuda.device(self.device):
             _check(L.fsim_batch_create(arr, len(structs), ctypes.byref(self.opt), ctypes.byref(h)))

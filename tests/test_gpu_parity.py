@@ -486,10 +486,9 @@ def test_every_kernel_variant_matches_oracle(variant):
     the lane kernel, the wave kernel, the ket-outer lane kernel, the 192-value
     lane kernel) and each waves-per-block setting gives the oracle's J and K
     for every quartet class: in FP64 within 1e-11, and with every kept
-    quartet an FP32 tile (tau_fp32 above every Schwarz bound) within 1e-5 of
+    quartet an FP32 tile (tau_fp32 above every Schwarz bound) within 1e-6 of
     max |J| and max |K| (every integral, strong ones included, then carries
-    FP32 rounding: about 1e-7 relative each, summed over ~1e3 terms of a
-    random density per element)."""
+    FP32 rounding, about 1e-7 relative each; measured 1.5e-7)."""
     b = spd_molecule()
     ctx = _ctx(b)
     ctx.schwarz_screen(tau=0.0)
@@ -510,7 +509,7 @@ def test_every_kernel_variant_matches_oracle(variant):
         dK = np.max(np.abs(r["K"].cpu().numpy() - Ko))
         print(f"variant {variant} wpb {wpb} all-FP32: |dJ|/max|J| = {dJ / sJ:.2e}, "
               f"|dK|/max|K| = {dK / sK:.2e}", flush=True)
-        assert dJ < 1e-5 * sJ and dK < 1e-5 * sK, (variant, wpb, dJ / sJ, dK / sK)
+        assert dJ < 1e-6 * sJ and dK < 1e-6 * sK, (variant, wpb, dJ / sJ, dK / sK)
         assert dJ > 0                                        # the FP32 kernels did run
 
 

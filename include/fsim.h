@@ -352,6 +352,17 @@ fsim_status fsim_batch_scf_info(const fsim_ctx *ctx, fsim_scf_info *info);
  * direct launches. */
 fsim_status fsim_set_graph(fsim_ctx *ctx, int32_t enable);
 
+/* enable != 0: every s/p quartet class ((ss|ss) .. (pp|pp)) of a Fock build
+ * runs in one resident launch per precision part instead of one launch per
+ * class: a global queue of (class, tile) items, heaviest class first, served
+ * by an atomic tile counter, each item evaluated by the class's ket-outer
+ * tile code (d classes keep their own launches, so a C/H batch needs one
+ * ERI launch per build and precision).  Per-launch profiling then reports
+ * the persistent launch as one record with bra_class = ket_class = 6.  The
+ * launch is captured in graphs like the others.  enable = 0 (default):
+ * per-class launches with the tuned variants.  Drops captured graphs. */
+fsim_status fsim_set_persistent(fsim_ctx *ctx, int32_t enable);
+
 /* Digest target of the Fock build (the J' and K' half-sums of Eq. fock).
  * enable != 0 (the default): every XCD of the GPU adds into its own private
  * copy of J' and K' (the XCD is read from the wave's XCC_ID register) and

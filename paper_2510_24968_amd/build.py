@@ -27,7 +27,7 @@ ERI_UNITS = [(f"eri_{_PC[b]}{_PC[k]}_{'f32' if p else 'f64'}",
              for b in range(6) for k in range(b + 1) for p in (0, 1)][::-1]
 SOURCES = [("eri_class.hip", name, defs) for name, defs in ERI_UNITS] + [
     (src, os.path.splitext(src)[0], []) for src in
-    ("stored.hip", "eri_dispatch.hip", "setup.hip", "linalg.hip", "mlp.hip", "noalloc.hip",
+    ("persistent.hip", "stored.hip", "eri_dispatch.hip", "setup.hip", "linalg.hip", "mlp.hip", "noalloc.hip",
      "api.cpp")]
 
 FLAGS = [
@@ -42,7 +42,7 @@ FLAGS = [
 
 # headers the ERI kernel units include (the other sources may include any)
 ERI_HEADERS = ("eri_kernels.h", "boys.h", "fsim_internal.h")
-ERI_SOURCES = ("eri_class.hip", "stored.hip")
+ERI_SOURCES = ("eri_class.hip", "stored.hip", "persistent.hip")
 
 
 def _newest_header(src):

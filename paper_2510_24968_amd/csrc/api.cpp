@@ -122,6 +122,10 @@ struct fsim_ctx {
     std::vector<double> Bb;            // [nmol][m][m]
     std::vector<double> Eprev_mol;
     std::vector<fsim_scf_info> mol_info;
+    // s/p quartet classes in one persistent launch per precision part (tile
+    // counters: one per part)
+    bool persistent = false;
+    int *pcounter = nullptr;
     // captured Fock build (hipGraph), one per precision
     bool graph_enabled = false;
     hipStream_t gstream = nullptr;
@@ -1215,6 +1219,18 @@ static void drop_graphs(fsim_ctx *c) {
 
 static constexpr int NXCD = 8;   // XCDs of an MI355X
 
+// Persistent queue slots (as persistent.hip orders them) and the class record
+// the profile uses for the persistent launch.
+static int persist_slot_bra(int k) { return k <= 1 || k == 3 ? 2 : (k == 5 ? 0 : 1); }
+static int persist_slot_ket(int k) { return k == 0 ? 2 : (k == 1 || k == 2 ? 1 : 0); }
+static int persist_slot_of(int X, int Y) {
+    for (int k = 0; k < PERSIST_SLOTS; ++k)
+        if (persist_slot_bra(k) == X && persist_slot_ket(k) == Y) return k;
+    return -1;
+}
+static constexpr int PERSIST_PROFILE_CLASS = NPCLASS;
+static constexpr int KO_STAGE_BYTES_MAX = 8192;   // per-wave LDS stage of a ket-outer tile
+
 // acc (optional): one shared pair of J'/K' accumulators to use instead of
 // the context's own (the allocation-free entry point).
 struct AccPair {
@@ -1243,14 +1259,56 @@ static fsim_status enqueue_build(fsim_ctx *c, const double *D, double *F, double
         HIPCHK(fill(Ksum, P, 0.0, s));
     }
     int nev = 0;
+    // s/p classes through the persistent queue kernel when every one of them
+    // fits its per-wave LDS stage (the stored-integral digest has its own kernel)
+    int pstage = 0;
+    bool persist = c->persistent && !(c->stored && !dref);
+    if (persist) {
+        for (int k = 0; k < PERSIST_SLOTS; ++k) {
+            const int X = persist_slot_bra(k);
+            const int per_prim = 32 + n_entries(pclass_l1(X), pclass_l2(X)) * 8;   // FP64 boxes
+            const int bytes = std::max(1, c->kept[X].kmax) * per_prim;
+            pstage = std::max(pstage, (bytes + 15) / 16 * 16);
+        }
+        persist = pstage <= KO_STAGE_BYTES_MAX;
+    }
+    PersistArgs pa[2];
+    bool have_pa[2] = {false, false};
+    if (persist) HIPCHK(fill_int(c->pcounter, 2, 0, s));
     // heaviest classes (highest L) first
     for (int X = NPCLASS - 1; X >= 0; --X)
         for (int Y = X; Y >= 0; --Y) {
             ClassLists &cl = c->lists[X][Y];
+            const int slot = persist ? persist_slot_of(X, Y) : -1;
             for (int part = 0; part < (mixed ? 2 : 1); ++part) {
                 const int li = mixed ? 1 + part : 0;
                 const TileList &tl = dref ? cl.delta[li]
                                           : (mixed ? (part == 0 ? cl.mix64 : cl.mix32) : cl.all64);
+                if (slot >= 0) {
+                    // queued for the persistent launch of this part
+                    PersistArgs &q = pa[part];
+                    if (!have_pa[part]) {
+                        q = PersistArgs{};
+                        have_pa[part] = true;
+                    }
+                    EriArgs &a = q.cls[slot];
+                    a = EriArgs{};
+                    a.bra = c->kept[X];
+                    a.ket = c->kept[Y];
+                    a.same_class = X == Y;
+                    a.tl = tl;
+                    a.D = D;
+                    a.Jh = Jacc;
+                    a.Kh = Kacc;
+                    a.xcd_stride = xp ? (long long)P : 0;
+                    a.nbf = c->nbf;
+                    a.mol_off = c->d_mol_off;
+                    a.mol_n = c->d_mol_n;
+                    a.boys = c->boys;
+                    a.stage_prims = std::max(1, c->kept[X].kmax);
+                    a.stage_bytes = pstage;
+                    continue;
+                }
                 if (tl.ntile == 0) continue;
                 if (prof) {
                     const ListStats &ls = mixed ? (part == 0 ? cl.sm64 : cl.sm32) : cl.s64;
@@ -1292,6 +1350,43 @@ static fsim_status enqueue_build(fsim_ctx *c, const double *D, double *F, double
                 if (prof) HIPCHK(hipEventRecord(c->ev[nev++], s));
             }
         }
+    for (int part = 0; part < 2; ++part) {
+        if (!have_pa[part]) continue;
+        PersistArgs &q = pa[part];
+        q.start[0] = 0;
+        int64_t nq = 0, npq = 0;
+        double fl = 0.0, flx = 0.0;
+        for (int k = 0; k < PERSIST_SLOTS; ++k) {
+            q.start[k + 1] = q.start[k] + q.cls[k].tl.ntile;
+            const ClassLists &cl = c->lists[persist_slot_bra(k)][persist_slot_ket(k)];
+            const int li = mixed ? 1 + part : 0;
+            const ListStats &ls = mixed ? (part == 0 ? cl.sm64 : cl.sm32) : cl.s64;
+            const double share = dref ? (double)cl.dnq[li] / std::max<int64_t>(1, ls.nq) : 1.0;
+            nq += dref ? cl.dnq[li] : ls.nq;
+            npq += (int64_t)(ls.npq * share);
+            fl += ls.flops * share;
+            flx += ls.flops_exec * share;
+        }
+        if (q.start[PERSIST_SLOTS] == 0) continue;
+        q.counter = c->pcounter + part;
+        q.stage_bytes = pstage;
+        q.boys = c->boys;
+        if (prof) {
+            fsim_class_profile pr{};
+            pr.bra_class = PERSIST_PROFILE_CLASS;
+            pr.ket_class = PERSIST_PROFILE_CLASS;
+            pr.fp32 = mixed && part == 1;
+            pr.tiles = q.start[PERSIST_SLOTS];
+            pr.quartets = nq;
+            pr.prim_quartets = npq;
+            pr.flops = fl;
+            pr.flops_exec = flx;
+            prof->push_back(pr);
+            HIPCHK(hipEventRecord(c->ev[nev++], s));
+        }
+        HIPCHK(launch_persistent(mixed && part == 1, q, s));
+        if (prof) HIPCHK(hipEventRecord(c->ev[nev++], s));
+    }
     if (xp) {
         HIPCHK(sum_copies(P, NXCD, c->priv, P, Jsum, s));
         HIPCHK(sum_copies(P, NXCD, c->priv + NXCD * P, P, Ksum, s));
@@ -1733,6 +1828,14 @@ extern "C" fsim_status fsim_set_tuning(fsim_ctx *c, const fsim_tuning *t, int32_
     return FSIM_OK;
 }
 
+extern "C" fsim_status fsim_set_persistent(fsim_ctx *c, int32_t enable) {
+    if (!c) return fail(FSIM_EINVAL, "ctx is NULL");
+    if (enable && !c->pcounter) HIPCHK(c->pool.alloc(&c->pcounter, 2));
+    c->persistent = enable != 0;
+    drop_graphs(c);
+    return FSIM_OK;
+}
+
 extern "C" fsim_status fsim_set_xcd_private(fsim_ctx *c, int32_t enable) {
     if (!c) return fail(FSIM_EINVAL, "NULL argument");
     c->xcd_private = enable != 0;
@@ -1769,8 +1872,9 @@ extern "C" fsim_status fsim_autotune(fsim_ctx *c, const double *D, fsim_precisio
     if (!c || !D) return fail(FSIM_EINVAL, "NULL argument");
     if (!c->screened) return fail(FSIM_ESTATE, "fsim_schwarz_screen must run before autotuning");
     hipStream_t s = (hipStream_t)stream;
-    const bool was = c->profiling;
+    const bool was = c->profiling, was_persistent = c->persistent;
     c->profiling = true;
+    c->persistent = false;   // every class is timed in its own launch
     double best[NPCLASS][NPCLASS][2];
     int bv[NPCLASS][NPCLASS][2], bw[NPCLASS][NPCLASS][2];
     for (int X = 0; X < NPCLASS; ++X)
@@ -1825,6 +1929,7 @@ extern "C" fsim_status fsim_autotune(fsim_ctx *c, const double *D, fsim_precisio
                 if (best[X][Y][f] < 1e299) c->tuned_ms[X][Y][f] = best[X][Y][f];
             }
     c->profiling = was;
+    c->persistent = was_persistent;
     drop_graphs(c);
     return st;
 }

@@ -552,13 +552,228 @@ __global__ __launch_bounds__(256, lane_min_waves(LA, LB, LC, LD, CA, CDC)) void 
 // quartet (cheap for small bra boxes) against loading every ket primitive
 // once per quartet instead of once per bra primitive.
 // ===========================================================================
-template <int LA, int LB, int LC, int LD, typename T, bool STORE, int CA, int CDC>
-__global__ __launch_bounds__(256) void k_eri_lane_ko(EriArgs a) {
+// Boys-function providers of the ket-outer tile body: the class kernels
+// stage the grid pre-divided for their own order L (boys.h); the persistent
+// kernel stages raw F_n(T_k) for every order its classes need.
+struct BoysStaged64 {
+    const double *tab;
+    template <int L>
+    __device__ __forceinline__ void eval(double T, double *F) const { boys_eval<L>(T, tab, F); }
+};
+struct BoysStagedMixed {
+    const float *tab;
+    template <int L>
+    __device__ __forceinline__ void eval(double T, double *F) const {
+        boys_eval_mixed<L>(T, tab, F);
+    }
+};
+
+// One tile (one bra pair x up to 64 kets) of the ket-outer kernel.  sp: this
+// wave's LDS slice for the staged bra primitives (4 + n_entries values each,
+// a.stage_prims of them).
+template <int LA, int LB, int LC, int LD, typename T, bool STORE, int CA, int CDC, typename BP>
+__device__ __forceinline__ void ko_tile(const EriArgs &a, const int tile, const BP &bp,
+                                        double *__restrict__ sp) {
     constexpr int L = LA + LB + LC + LD, LAB = LA + LB;
     constexpr int NA = ncart(LA), NB = ncart(LB), NC = ncart(LC), ND = ncart(LD);
     constexpr int NCD = NC * ND, NHAB = nherm(LAB), NH = nherm(L);
     constexpr int NEB = n_entries(LA, LB), NEK = n_entries(LC, LD);
     constexpr int NCHA = (NA + CA - 1) / CA, NCHCD = (NCD + CDC - 1) / CDC;
+    constexpr bool F32 = std::is_same<T, float>::value;
+    const int lane = threadIdx.x & 63;
+    const T *__restrict__ Eb = etab<T>(a.bra);
+    const T *__restrict__ Ek = etab<T>(a.ket);
+    const size_t nb = a.bra.n, nk = a.ket.n;
+    const long long xoff = (!STORE && a.xcd_stride) ? xcd_index() * a.xcd_stride : 0;
+    T *__restrict__ se = (T *)(sp + 4 * a.stage_prims);
+    int bra, ket;
+    bool active;
+    if constexpr (STORE) {
+        bra = __builtin_amdgcn_readfirstlane(a.st_bra[tile]);
+        ket = a.st_ket[tile * 64 + lane];
+        active = ket >= 0;
+        if (!active) ket = 0;
+    } else {
+        const int b = tile_bra(a.tl, tile);
+        bra = __builtin_amdgcn_readfirstlane(a.tl.bra[b]);
+        const int k0 = a.tl.ket_lo[b] + (tile - a.tl.tile_start[b]) * TILE;
+        ket = k0 + lane;
+        active = ket < a.tl.ket_hi[b];
+        if (!active) ket = k0;
+    }
+    const int nbp = __builtin_amdgcn_readfirstlane(a.bra.nprim[bra]);
+    const int nkp = active ? a.ket.nprim[ket] : 0;
+    const int mol = __builtin_amdgcn_readfirstlane(a.bra.mol[bra]);
+    const long long mbase = STORE ? 0 : a.mol_off[mol];
+    const int N = STORE ? 0 : a.mol_n[mol];
+    const double *__restrict__ D = STORE ? nullptr : a.D + mbase;
+    double *__restrict__ Jh = STORE ? nullptr : a.Jh + xoff + mbase;
+    double *__restrict__ Kh = STORE ? nullptr : a.Kh + xoff + mbase;
+    const int f1 = __builtin_amdgcn_readfirstlane(a.bra.bf1[bra]);
+    const int f2 = __builtin_amdgcn_readfirstlane(a.bra.bf2[bra]);
+    const int f3 = a.ket.bf1[ket], f4 = a.ket.bf2[ket];
+    double fac = active ? 1.0 : 0.0;
+    if (a.bra.sh1[bra] == a.bra.sh2[bra]) fac *= 0.5;
+    if (a.ket.sh1[ket] == a.ket.sh2[ket]) fac *= 0.5;
+    if (a.same_class && ket == bra) fac *= 0.5;
+    long long soff = 0;
+    int st0 = 0, st1 = 0, st2 = 0, st3 = 0;
+    if constexpr (STORE) {
+        if (active) {
+            const size_t q = (size_t)tile * 64 + lane;
+            soff = a.st_off[q];
+            st0 = a.st_stride[q * 4 + 0];
+            st1 = a.st_stride[q * 4 + 1];
+            st2 = a.st_stride[q * 4 + 2];
+            st3 = a.st_stride[q * 4 + 3];
+        }
+    }
+
+    // stage the bra primitives: p, P (4 doubles) and the Hermite boxes
+    for (int x = lane; x < nbp * 4; x += 64) {
+        const int s = x >> 2, f = x & 3;
+        sp[x] = f == 0 ? a.bra.p[(size_t)s * nb + bra] : a.bra.P[((size_t)s * 3 + f - 1) * nb + bra];
+    }
+    for (int x = lane; x < nbp * NEB; x += 64) se[x] = Eb[(size_t)x * nb + bra];
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+
+    static_for<NCHA * NCHCD>([&](auto ch_) {
+        constexpr int ch = decltype(ch_)::value;
+        constexpr int A0 = (ch / NCHCD) * CA, A1 = cmin(A0 + CA, NA);
+        constexpr int CD0 = (ch % NCHCD) * CDC, CD1 = cmin(CD0 + CDC, NCD);
+        constexpr int NAc = A1 - A0, NABc = NAc * NB, NCDc = CD1 - CD0;
+        constexpr int EK0 = box_off(LC, LD, CD0);
+        constexpr int EK1 = CD1 < NCD ? box_off(LC, LD, CD1) : NEK;
+        T out[NABc][NCDc];
+#pragma unroll
+        for (int x = 0; x < NABc; ++x)
+#pragma unroll
+            for (int y = 0; y < NCDc; ++y) out[x][y] = T(0);
+
+        for (int j = 0; j < nkp; ++j) {
+            // this ket primitive, held across the bra primitives
+            const double q = a.ket.p[(size_t)j * nk + ket];
+            const double Kx = a.ket.P[((size_t)j * 3 + 0) * nk + ket];
+            const double Ky = a.ket.P[((size_t)j * 3 + 1) * nk + ket];
+            const double Kz = a.ket.P[((size_t)j * 3 + 2) * nk + ket];
+            T ek[EK1 - EK0];
+            const T *__restrict__ ekp = Ek + (size_t)j * NEK * nk + ket;
+#pragma unroll
+            for (int e = EK0; e < EK1; ++e) {
+                T ev = ekp[(size_t)e * nk];
+                ek[e - EK0] = ev;
+            }
+            for (int i = 0; i < nbp; ++i) {
+                const double p = sp[i * 4 + 0];
+                const double X = sp[i * 4 + 1] - Kx, Y = sp[i * 4 + 2] - Ky,
+                             Z = sp[i * 4 + 3] - Kz;
+                T src[L + 1];
+                if constexpr (F32) {
+                    // FP32 tile: FP32 Taylor step, FP64 recursion and
+                    // prefactor, sources rounded to FP32
+                    const double rs = rsqrt(p + q);
+                    const double alpha = p * q * (rs * rs);
+                    double F[L + 1];
+                    bp.template eval<L>(alpha * (X * X + Y * Y + Z * Z), F);
+                    double m = rs;
+#pragma unroll
+                    for (int n = 0; n <= L; ++n) {
+                        src[n] = (float)(F[n] * m);
+                        m *= -2.0 * alpha;
+                    }
+                } else {
+                    const double rs = rsqrt(p + q);
+                    const double alpha = p * q * (rs * rs);
+                    double F[L + 1];
+                    bp.template eval<L>(alpha * (X * X + Y * Y + Z * Z), F);
+                    double m = rs;
+#pragma unroll
+                    for (int n = 0; n <= L; ++n) {
+                        src[n] = T(F[n] * m);
+                        m *= -2.0 * alpha;
+                    }
+                }
+                T r[NH];
+                hermite_r<L, T>(src, T(X), T(Y), T(Z), r);
+                // ket step for this primitive quartet
+                T V[NCDc][NHAB];
+                static_for<NCDc>([&](auto cdl_) {
+                    constexpr int cdl = decltype(cdl_)::value;
+                    constexpr int cd = CD0 + cdl;
+                    constexpr int bx = box_dim(LC, LD, cd, 0), by = box_dim(LC, LD, cd, 1),
+                                  bz = box_dim(LC, LD, cd, 2);
+                    constexpr int eo = box_off(LC, LD, cd);
+                    static_for<NHAB>([&](auto h_) { V[cdl][decltype(h_)::value] = T(0); });
+                    static_for<bx + 1>([&](auto ta_) {
+                        constexpr int ta = decltype(ta_)::value;
+                        static_for<by + 1>([&](auto nu_) {
+                            constexpr int nu = decltype(nu_)::value;
+                            static_for<bz + 1>([&](auto ph_) {
+                                constexpr int ph = decltype(ph_)::value;
+                                constexpr int e = eo + (ta * (by + 1) + nu) * (bz + 1) + ph;
+                                T ev = ek[e - EK0];
+                                if constexpr ((ta + nu + ph) & 1) ev = -ev;
+                                static_for<NHAB>([&](auto h_) {
+                                    constexpr int h = decltype(h_)::value;
+                                    constexpr int ri = hidx(hidx_t(h) + ta, hidx_u(h) + nu,
+                                                            hidx_v(h) + ph);
+                                    V[cdl][h] = fma(ev, r[ri], V[cdl][h]);
+                                });
+                            });
+                        });
+                    });
+                });
+                // bra step for this primitive quartet (boxes from LDS)
+                const T *__restrict__ eb = se + i * NEB;
+                static_for<NABc>([&](auto abl_) {
+                    constexpr int abl = decltype(abl_)::value;
+                    constexpr int ab = (A0 + abl / NB) * NB + abl % NB;
+                    constexpr int ax = box_dim(LA, LB, ab, 0), ay = box_dim(LA, LB, ab, 1),
+                                  az = box_dim(LA, LB, ab, 2);
+                    constexpr int ao = box_off(LA, LB, ab);
+                    static_for<ax + 1>([&](auto t_) {
+                        constexpr int t = decltype(t_)::value;
+                        static_for<ay + 1>([&](auto u_) {
+                            constexpr int u = decltype(u_)::value;
+                            static_for<az + 1>([&](auto v_) {
+                                constexpr int v = decltype(v_)::value;
+                                constexpr int e = ao + (t * (ay + 1) + u) * (az + 1) + v;
+                                const T ebv = eb[e];
+                                static_for<NCDc>([&](auto cdl_) {
+                                    constexpr int cdl = decltype(cdl_)::value;
+                                    out[abl][cdl] = fma(ebv, V[cdl][hidx(t, u, v)], out[abl][cdl]);
+                                });
+                            });
+                        });
+                    });
+                });
+            }
+        }
+        if constexpr (STORE) {
+            if (active) {
+                static_for<NABc>([&](auto abl_) {
+                    constexpr int abl = decltype(abl_)::value;
+                    constexpr int ia = A0 + abl / NB, ib = abl % NB;
+                    static_for<NCDc>([&](auto cdl_) {
+                        constexpr int cdl = decltype(cdl_)::value;
+                        constexpr int ic = (CD0 + cdl) / ND, id = (CD0 + cdl) % ND;
+                        a.out[soff + ia * st0 + ib * st1 + ic * st2 + id * st3] =
+                            (double)out[abl][cdl];
+                    });
+                });
+            }
+        } else {
+            digest_chunk<LA, LB, LC, LD, T, A0, A1, CD0, CD1>(out, D, Jh, Kh, N, f1, f2, f3,
+                                                              f4, fac, active);
+        }
+    });
+}
+
+template <int LA, int LB, int LC, int LD, typename T, bool STORE, int CA, int CDC>
+__global__ __launch_bounds__(256) void k_eri_lane_ko(EriArgs a) {
+    constexpr int L = LA + LB + LC + LD;
     // Boys grid in LDS: FP64 for FP64 tiles, FP32 (5 terms, the Taylor step
     // only) for FP32 tiles
     constexpr bool F32 = std::is_same<T, float>::value;
@@ -567,204 +782,16 @@ __global__ __launch_bounds__(256) void k_eri_lane_ko(EriArgs a) {
     if constexpr (F32) boys_stage32(tab, a.boys, L);
     else boys_stage(tab, a.boys, L);
     __syncthreads();
-    const int lane = threadIdx.x & 63;
     const int wpb = blockDim.x >> 6;
     const int ntile = STORE ? a.st_ntile : a.tl.ntile;
-    const T *__restrict__ Eb = etab<T>(a.bra);
-    const T *__restrict__ Ek = etab<T>(a.ket);
-    const size_t nb = a.bra.n, nk = a.ket.n;
-    const long long xoff = (!STORE && a.xcd_stride) ? xcd_index() * a.xcd_stride : 0;
     // every bra primitive of the tile is staged (the launch checks kmax fits)
     double *__restrict__ sp = (double *)(stage_lds + (size_t)(threadIdx.x >> 6) * a.stage_bytes);
-    T *__restrict__ se = (T *)(sp + 4 * a.stage_prims);
-
+    using BP = std::conditional_t<F32, BoysStagedMixed, BoysStaged64>;
+    const BP bp{tab};
     for (int tile0 = blockIdx.x * wpb + (threadIdx.x >> 6); tile0 < ntile;
-         tile0 += gridDim.x * wpb) {
-        const int tile = __builtin_amdgcn_readfirstlane(tile0);
-        int bra, ket;
-        bool active;
-        if constexpr (STORE) {
-            bra = __builtin_amdgcn_readfirstlane(a.st_bra[tile]);
-            ket = a.st_ket[tile * 64 + lane];
-            active = ket >= 0;
-            if (!active) ket = 0;
-        } else {
-            const int b = tile_bra(a.tl, tile);
-            bra = __builtin_amdgcn_readfirstlane(a.tl.bra[b]);
-            const int k0 = a.tl.ket_lo[b] + (tile - a.tl.tile_start[b]) * TILE;
-            ket = k0 + lane;
-            active = ket < a.tl.ket_hi[b];
-            if (!active) ket = k0;
-        }
-        const int nbp = __builtin_amdgcn_readfirstlane(a.bra.nprim[bra]);
-        const int nkp = active ? a.ket.nprim[ket] : 0;
-        const int mol = __builtin_amdgcn_readfirstlane(a.bra.mol[bra]);
-        const long long mbase = STORE ? 0 : a.mol_off[mol];
-        const int N = STORE ? 0 : a.mol_n[mol];
-        const double *__restrict__ D = STORE ? nullptr : a.D + mbase;
-        double *__restrict__ Jh = STORE ? nullptr : a.Jh + xoff + mbase;
-        double *__restrict__ Kh = STORE ? nullptr : a.Kh + xoff + mbase;
-        const int f1 = __builtin_amdgcn_readfirstlane(a.bra.bf1[bra]);
-        const int f2 = __builtin_amdgcn_readfirstlane(a.bra.bf2[bra]);
-        const int f3 = a.ket.bf1[ket], f4 = a.ket.bf2[ket];
-        double fac = active ? 1.0 : 0.0;
-        if (a.bra.sh1[bra] == a.bra.sh2[bra]) fac *= 0.5;
-        if (a.ket.sh1[ket] == a.ket.sh2[ket]) fac *= 0.5;
-        if (a.same_class && ket == bra) fac *= 0.5;
-        long long soff = 0;
-        int st0 = 0, st1 = 0, st2 = 0, st3 = 0;
-        if constexpr (STORE) {
-            if (active) {
-                const size_t q = (size_t)tile * 64 + lane;
-                soff = a.st_off[q];
-                st0 = a.st_stride[q * 4 + 0];
-                st1 = a.st_stride[q * 4 + 1];
-                st2 = a.st_stride[q * 4 + 2];
-                st3 = a.st_stride[q * 4 + 3];
-            }
-        }
-
-        // stage the bra primitives: p, P (4 doubles) and the Hermite boxes
-        for (int x = lane; x < nbp * 4; x += 64) {
-            const int s = x >> 2, f = x & 3;
-            sp[x] = f == 0 ? a.bra.p[(size_t)s * nb + bra] : a.bra.P[((size_t)s * 3 + f - 1) * nb + bra];
-        }
-        for (int x = lane; x < nbp * NEB; x += 64) se[x] = Eb[(size_t)x * nb + bra];
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-
-        static_for<NCHA * NCHCD>([&](auto ch_) {
-            constexpr int ch = decltype(ch_)::value;
-            constexpr int A0 = (ch / NCHCD) * CA, A1 = cmin(A0 + CA, NA);
-            constexpr int CD0 = (ch % NCHCD) * CDC, CD1 = cmin(CD0 + CDC, NCD);
-            constexpr int NAc = A1 - A0, NABc = NAc * NB, NCDc = CD1 - CD0;
-            constexpr int EK0 = box_off(LC, LD, CD0);
-            constexpr int EK1 = CD1 < NCD ? box_off(LC, LD, CD1) : NEK;
-            T out[NABc][NCDc];
-#pragma unroll
-            for (int x = 0; x < NABc; ++x)
-#pragma unroll
-                for (int y = 0; y < NCDc; ++y) out[x][y] = T(0);
-
-            for (int j = 0; j < nkp; ++j) {
-                // this ket primitive, held across the bra primitives
-                const double q = a.ket.p[(size_t)j * nk + ket];
-                const double Kx = a.ket.P[((size_t)j * 3 + 0) * nk + ket];
-                const double Ky = a.ket.P[((size_t)j * 3 + 1) * nk + ket];
-                const double Kz = a.ket.P[((size_t)j * 3 + 2) * nk + ket];
-                T ek[EK1 - EK0];
-                const T *__restrict__ ekp = Ek + (size_t)j * NEK * nk + ket;
-#pragma unroll
-                for (int e = EK0; e < EK1; ++e) {
-                    T ev = ekp[(size_t)e * nk];
-                    ek[e - EK0] = ev;
-                }
-                for (int i = 0; i < nbp; ++i) {
-                    const double p = sp[i * 4 + 0];
-                    const double X = sp[i * 4 + 1] - Kx, Y = sp[i * 4 + 2] - Ky,
-                                 Z = sp[i * 4 + 3] - Kz;
-                    T src[L + 1];
-                    if constexpr (F32) {
-                        // FP32 tile: FP32 Taylor step, FP64 recursion and
-                        // prefactor, sources rounded to FP32
-                        const double rs = rsqrt(p + q);
-                        const double alpha = p * q * (rs * rs);
-                        double F[L + 1];
-                        boys_eval_mixed<L>(alpha * (X * X + Y * Y + Z * Z), tab, F);
-                        double m = rs;
-#pragma unroll
-                        for (int n = 0; n <= L; ++n) {
-                            src[n] = (float)(F[n] * m);
-                            m *= -2.0 * alpha;
-                        }
-                    } else {
-                        const double rs = rsqrt(p + q);
-                        const double alpha = p * q * (rs * rs);
-                        double F[L + 1];
-                        boys_eval<L>(alpha * (X * X + Y * Y + Z * Z), tab, F);
-                        double m = rs;
-#pragma unroll
-                        for (int n = 0; n <= L; ++n) {
-                            src[n] = T(F[n] * m);
-                            m *= -2.0 * alpha;
-                        }
-                    }
-                    T r[NH];
-                    hermite_r<L, T>(src, T(X), T(Y), T(Z), r);
-                    // ket step for this primitive quartet
-                    T V[NCDc][NHAB];
-                    static_for<NCDc>([&](auto cdl_) {
-                        constexpr int cdl = decltype(cdl_)::value;
-                        constexpr int cd = CD0 + cdl;
-                        constexpr int bx = box_dim(LC, LD, cd, 0), by = box_dim(LC, LD, cd, 1),
-                                      bz = box_dim(LC, LD, cd, 2);
-                        constexpr int eo = box_off(LC, LD, cd);
-                        static_for<NHAB>([&](auto h_) { V[cdl][decltype(h_)::value] = T(0); });
-                        static_for<bx + 1>([&](auto ta_) {
-                            constexpr int ta = decltype(ta_)::value;
-                            static_for<by + 1>([&](auto nu_) {
-                                constexpr int nu = decltype(nu_)::value;
-                                static_for<bz + 1>([&](auto ph_) {
-                                    constexpr int ph = decltype(ph_)::value;
-                                    constexpr int e = eo + (ta * (by + 1) + nu) * (bz + 1) + ph;
-                                    T ev = ek[e - EK0];
-                                    if constexpr ((ta + nu + ph) & 1) ev = -ev;
-                                    static_for<NHAB>([&](auto h_) {
-                                        constexpr int h = decltype(h_)::value;
-                                        constexpr int ri = hidx(hidx_t(h) + ta, hidx_u(h) + nu,
-                                                                hidx_v(h) + ph);
-                                        V[cdl][h] = fma(ev, r[ri], V[cdl][h]);
-                                    });
-                                });
-                            });
-                        });
-                    });
-                    // bra step for this primitive quartet (boxes from LDS)
-                    const T *__restrict__ eb = se + i * NEB;
-                    static_for<NABc>([&](auto abl_) {
-                        constexpr int abl = decltype(abl_)::value;
-                        constexpr int ab = (A0 + abl / NB) * NB + abl % NB;
-                        constexpr int ax = box_dim(LA, LB, ab, 0), ay = box_dim(LA, LB, ab, 1),
-                                      az = box_dim(LA, LB, ab, 2);
-                        constexpr int ao = box_off(LA, LB, ab);
-                        static_for<ax + 1>([&](auto t_) {
-                            constexpr int t = decltype(t_)::value;
-                            static_for<ay + 1>([&](auto u_) {
-                                constexpr int u = decltype(u_)::value;
-                                static_for<az + 1>([&](auto v_) {
-                                    constexpr int v = decltype(v_)::value;
-                                    constexpr int e = ao + (t * (ay + 1) + u) * (az + 1) + v;
-                                    const T ebv = eb[e];
-                                    static_for<NCDc>([&](auto cdl_) {
-                                        constexpr int cdl = decltype(cdl_)::value;
-                                        out[abl][cdl] = fma(ebv, V[cdl][hidx(t, u, v)], out[abl][cdl]);
-                                    });
-                                });
-                            });
-                        });
-                    });
-                }
-            }
-            if constexpr (STORE) {
-                if (active) {
-                    static_for<NABc>([&](auto abl_) {
-                        constexpr int abl = decltype(abl_)::value;
-                        constexpr int ia = A0 + abl / NB, ib = abl % NB;
-                        static_for<NCDc>([&](auto cdl_) {
-                            constexpr int cdl = decltype(cdl_)::value;
-                            constexpr int ic = (CD0 + cdl) / ND, id = (CD0 + cdl) % ND;
-                            a.out[soff + ia * st0 + ib * st1 + ic * st2 + id * st3] =
-                                (double)out[abl][cdl];
-                        });
-                    });
-                }
-            } else {
-                digest_chunk<LA, LB, LC, LD, T, A0, A1, CD0, CD1>(out, D, Jh, Kh, N, f1, f2, f3,
-                                                                  f4, fac, active);
-            }
-        });
-    }
+         tile0 += gridDim.x * wpb)
+        ko_tile<LA, LB, LC, LD, T, STORE, CA, CDC>(a, __builtin_amdgcn_readfirstlane(tile0), bp,
+                                                   sp);
 }
 
 // ===========================================================================

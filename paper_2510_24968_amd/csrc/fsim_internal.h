@@ -197,6 +197,22 @@ hipError_t launch_one_electron_impl(const ShellsDev &sh, const double *boys, int
 // one quartet class and precision (eri_class.hip, compiled per class)
 template <int X, int Y, bool F32>
 hipError_t launch_eri_unit(bool store, int variant, int wpb, const EriArgs &a, hipStream_t s);
+// Persistent launch over the s/p quartet classes (persistent.hip): queue
+// slot k holds the tiles of class (persist_bra(k) | persist_ket(k)), slots
+// 0..5 = (pp|pp) (pp|ps) (ps|ps) (pp|ss) (ps|ss) (ss|ss); start[k] is the
+// first queue position of slot k, start[6] the total.  *counter must be 0
+// at launch.  Every slot's stage_prims x (4 + n_entries) FP64/T values must
+// fit stage_bytes, the per-wave LDS slice.
+constexpr int PERSIST_SLOTS = 6;
+constexpr int PERSIST_BUDGET = 128;   // lane-kernel live-value budget of the tile bodies
+struct PersistArgs {
+    EriArgs cls[PERSIST_SLOTS];
+    int start[PERSIST_SLOTS + 1];
+    int *counter;
+    int stage_bytes;
+    const double *boys;
+};
+hipError_t launch_persistent(bool fp32, const PersistArgs &p, hipStream_t s);
 // digest of stored blocks (stored.hip): a.out = the class's store, a.tl its
 // FP64 tile list
 hipError_t launch_digest_stored(int bra_pc, int ket_pc, int wpb, const EriArgs &a,

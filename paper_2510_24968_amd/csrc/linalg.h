@@ -14,6 +14,7 @@ struct DiisPtrs {
 };
 
 hipError_t fill(double *x, size_t n, double v, hipStream_t s);
+hipError_t fill_int(int *x, size_t n, int v, hipStream_t s);
 // dst[i] = sum_{k < ncopy} src[k * stride + i] for i < n
 hipError_t sum_copies(size_t n, int ncopy, const double *src, size_t stride, double *dst,
                       hipStream_t s);

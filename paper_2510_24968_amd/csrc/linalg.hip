@@ -9,6 +9,12 @@ __global__ void k_fill(double *x, size_t n, double v) {
         x[i] = v;
 }
 
+__global__ void k_fill_int(int *x, size_t n, int v) {
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n;
+         i += (size_t)gridDim.x * blockDim.x)
+        x[i] = v;
+}
+
 __global__ void k_sum_copies(size_t n, int ncopy, const double *__restrict__ src, size_t stride,
                              double *dst) {
     for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n;
@@ -399,6 +405,10 @@ static inline dim3 grid_for(size_t n) {
 
 hipError_t fill(double *x, size_t n, double v, hipStream_t s) {
     hipLaunchKernelGGL(k_fill, grid_for(n), dim3(256), 0, s, x, n, v);
+    return hipGetLastError();
+}
+hipError_t fill_int(int *x, size_t n, int v, hipStream_t s) {
+    hipLaunchKernelGGL(k_fill_int, grid_for(n), dim3(256), 0, s, x, n, v);
     return hipGetLastError();
 }
 hipError_t sum_copies(size_t n, int ncopy, const double *src, size_t stride, double *dst,

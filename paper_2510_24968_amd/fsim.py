@@ -72,7 +72,7 @@ class _Tuning(ctypes.Structure):
                 ("kket", ctypes.c_int32), ("pad", ctypes.c_int32), ("ms", ctypes.c_double)]
 
 
-PAIR_CLASS = ("ss", "ps", "pp", "ds", "dp", "dd")
+PAIR_CLASS = ("ss", "ps", "pp", "ds", "dp", "dd", "sp*")   # "sp*": the persistent s/p launch
 NVARIANT = 6
 
 
@@ -116,6 +116,7 @@ def lib():
         "fsim_batch_scf_info": [vp, vp],
         "fsim_set_graph": [vp, i32],
         "fsim_set_xcd_private": [vp, i32],
+        "fsim_set_persistent": [vp, i32],
         "fsim_set_tuning": [vp, vp, i32],
         "fsim_get_tuning": [vp, vp, i32, ctypes.POINTER(i32)],
         "fsim_autotune": [vp, vp, ctypes.c_int, vp],
@@ -288,6 +289,11 @@ class Context:
         """Per-XCD private J'/K' accumulators (default on) or one shared copy."""
         _check(lib().fsim_set_xcd_private(self.h, 1 if enable else 0))
 
+    def set_persistent(self, enable=True):
+        """s/p quartet classes in one persistent queue launch per precision
+        part (fsim_set_persistent)."""
+        _check(lib().fsim_set_persistent(self.h, 1 if enable else 0))
+
     def set_profiling(self, enable=True):
         _check(lib().fsim_set_profiling(self.h, 1 if enable else 0))
 
@@ -455,9 +461,12 @@ class Batch(Context):
         _check(lib().fsim_one_electron(self.h, _ptr(S), _ptr(H), _ptr(X), _stream()))
         return S, H, X
 
-    def scf(self, precision="fp64", max_iter=100, D0=None, verbose=False, refine=True):
+    def scf(self, precision="fp64", max_iter=100, D0=None, verbose=False, refine=True,
+            stop_fraction=None):
         """All molecules at once; each molecule's energy and the iteration at
-        which it first met the convergence test are returned."""
+        which it first met the convergence test are returned.  stop_fraction:
+        end as soon as that share of the molecules meets the test in the same
+        step."""
         if self.screen_stats is None:
             self.schwarz_screen(want_q=False)
         self.scf_reset()
@@ -478,6 +487,9 @@ class Batch(Context):
                       f"max rmsD={info['rms_dD']:.2e} converged {int((first_conv >= 0).sum())}"
                       f"/{self.nmol}", flush=True)
             if info["converged"]:
+                break
+            if stop_fraction is not None and \
+                    sum(1 for r in per if r["converged"]) >= stop_fraction * self.nmol:
                 break
         E = np.array([r["E_total"] for r in per])
         res = {"E_total": E, "iterations": info["iter"], "converged": bool(info["converged"]),

@@ -433,15 +433,26 @@ class GuessNet:
         X = self.to_bf16(torch.as_tensor(feats, dtype=torch.float32, device=self.dev))
         return self.infer(X).cpu().numpy()
 
-    def state(self):
+    def state(self, full=False):
+        """Weights and biases; with full, also the Adam moments and step, so
+        that training can continue in another process."""
         st = {f"W{k}": self.W[k].cpu().numpy() for k in range(3)}
         st.update({f"b{k}": self.b[k].cpu().numpy() for k in range(3)})
+        if full:
+            st.update({f"m1_{k}": t.cpu().numpy() for k, t in enumerate(self.m1)})
+            st.update({f"m2_{k}": t.cpu().numpy() for k, t in enumerate(self.m2)})
+            st["step"] = np.array(self.step)
         return st
 
     def load(self, st):
         for k in range(3):
             self.W[k].copy_(torch.as_tensor(st[f"W{k}"]))
             self.b[k].copy_(torch.as_tensor(st[f"b{k}"]))
+        if "step" in st:
+            for k in range(len(self.m1)):
+                self.m1[k].copy_(torch.as_tensor(st[f"m1_{k}"]))
+                self.m2[k].copy_(torch.as_tensor(st[f"m2_{k}"]))
+            self.step = int(st["step"])
         self.refresh()
 
 
@@ -464,36 +475,68 @@ def training_molecules(n_chain, n_water, seed0=5_000_000):
     return mols
 
 
-def converged_densities(mols, chunk=128, tau=1e-10, max_iter=60, log=None):
-    """FP64 batched SCF (this library) of every molecule; returns the
-    densities of those that converged and their indices."""
-    out, idx = [], []
-    for c0 in range(0, len(mols), chunk):
-        part = mols[c0:c0 + chunk]
-        bt = fsim.Batch(part, tau=tau, conv_rms_dD=1e-7, conv_dE=1e-9)
+def training_set(n, seed0=5_000_000):
+    """The configured training population as one interleaved list: molecule
+    i (seed seed0 + i) is an H chain (even 4..32 atoms, spacing U[1.2, 2.0]
+    bohr) for even i and a water-like cluster of 2..16 molecules for odd i,
+    so that any contiguous slice holds both kinds half and half."""
+    import synth
+    mols = []
+    for i in range(n):
+        rng = np.random.default_rng(seed0 + i)
+        if i % 2 == 0:
+            mols.append(synth.h_chain(2 * int(rng.integers(2, 17)), float(rng.uniform(1.2, 2.0))))
+        else:
+            mols.append(synth.water_cluster(int(rng.integers(2, 17)), seed0 + i))
+    return mols
+
+
+def converged_densities(mols, chunk=128, tau=1e-10, max_iter=60, conv_rms_dD=1e-7,
+                        conv_dE=1e-9, stop_fraction=None, log=None):
+    """FP64 batched SCF (this library) of every molecule, in size-sorted
+    chunks (a chunk may end once stop_fraction of it has converged); returns
+    the densities of those that meet the convergence test at the chunk's
+    last step, and their indices."""
+    import synth
+    order = sorted(range(len(mols)), key=lambda i: synth.nbf_of(mols[i]))
+    out, idx = {}, []
+    for c0 in range(0, len(order), chunk):
+        ids = order[c0:c0 + chunk]
+        part = [mols[i] for i in ids]
+        bt = fsim.Batch(part, tau=tau, conv_rms_dD=conv_rms_dD, conv_dE=conv_dE)
         bt.set_graph(True)
         t0 = time.time()
-        r = bt.scf(max_iter=max_iter)
+        r = bt.scf(max_iter=max_iter, stop_fraction=stop_fraction, verbose=log is not None)
         blocks = bt.unpack(r["D"])
         ok = [m for m, rec in enumerate(r["per_molecule"]) if rec["converged"]]
         for m in ok:
-            out.append(blocks[m].cpu().numpy())
-            idx.append(c0 + m)
+            out[ids[m]] = blocks[m].cpu().numpy()
+            idx.append(ids[m])
         if log:
             log(f"SCF chunk {c0 // chunk + 1}: {len(ok)}/{len(part)} converged after "
                 f"{r['iterations']} iterations, {time.time() - t0:.1f} s")
         bt.close()
-    return out, idx
+    idx.sort()
+    return [out[i] for i in idx], idx
 
 
-def dataset(mols, dens):
-    fs, ts, ms = [], [], []
-    for b, D in zip(mols, dens):
-        s = pair_samples(b, D)
-        fs.append(s["feats"])
-        ts.append(s["target"])
-        ms.append(s["mask"])
-    return np.concatenate(fs), np.concatenate(ts), np.concatenate(ms)
+def _samples_of(args):
+    b, D = args
+    s = pair_samples(b, D)
+    return s["feats"], s["target"], s["mask"]
+
+
+def dataset(mols, dens, workers=1):
+    """Shell-pair samples (features, targets, masks) of every molecule; the
+    numpy work can run in a process pool."""
+    if workers > 1:
+        import multiprocessing as mp
+        with mp.get_context("fork").Pool(workers) as pool:
+            parts = pool.map(_samples_of, list(zip(mols, dens)), chunksize=16)
+    else:
+        parts = [_samples_of(a) for a in zip(mols, dens)]
+    return (np.concatenate([p[0] for p in parts]), np.concatenate([p[1] for p in parts]),
+            np.concatenate([p[2] for p in parts]))
 
 
 def predicted_density(net, basis):
@@ -528,13 +571,19 @@ def evaluate(net, mols, tau=1e-11, max_iter=60, log=None):
     learned guess (one batch each); per-molecule iterations to convergence,
     wall time and the converged energies of both runs."""
     guesses, infos = [], []
+    torch.cuda.synchronize()
+    tg = time.time()
     for b in mols:
         ctx = fsim.Context(b, tau=tau)
         D, info = learned_guess(net, ctx, b)
         guesses.append(D)
         infos.append(info)
         ctx.close()
-    res = {}
+    torch.cuda.synchronize()
+    # features, inference, assembly, purification and fallbacks, with the
+    # one-molecule contexts they need
+    guess_seconds = time.time() - tg
+    res = {"guess_seconds": guess_seconds}
     for name in ("core", "learned"):
         bt = fsim.Batch(mols, tau=tau, conv_rms_dD=1e-8, conv_dE=1e-10)
         bt.set_graph(True)
@@ -553,7 +602,50 @@ def evaluate(net, mols, tau=1e-11, max_iter=60, log=None):
                 f"per-molecule median {med}, unconverged {int((fc < 0).sum())}")
         bt.close()
     res["guess_info"] = infos
+    res["learned"]["seconds_with_guess"] = res["learned"]["seconds"] + guess_seconds
+    if log:
+        log(f"learned guess construction {guess_seconds:.1f} s; learned total "
+            f"{res['learned']['seconds_with_guess']:.1f} s vs core {res['core']['seconds']:.1f} s")
     return res
+
+
+def stream_part(a, log):
+    """One part of the training set: converged densities from batched SCFs,
+    their shell-pair samples, and a.epochs epochs of Adam continuing from the
+    saved state; the full state and a record of the part are written to
+    a.out."""
+    import json
+    import os
+    t0 = time.time()
+    full = training_set(a.total)
+    per = (a.total + a.stream_parts - 1) // a.stream_parts
+    lo, hi = a.stream_part * per, min(a.total, (a.stream_part + 1) * per)
+    mols = full[lo:hi]
+    log(f"part {a.stream_part + 1}/{a.stream_parts}: molecules {lo}..{hi - 1}")
+    dens, idx = converged_densities(mols, chunk=512, max_iter=40, conv_rms_dD=a.conv, conv_dE=0.0,
+                                    stop_fraction=0.98, log=log)
+    t_scf = time.time() - t0
+    mols = [mols[i] for i in idx]
+    log(f"{len(mols)} converged densities in {t_scf:.1f} s")
+    t1 = time.time()
+    X, T, M = dataset(mols, dens, workers=a.workers)
+    t_feat = time.time() - t1
+    log(f"{X.shape[0]} shell-pair samples in {t_feat:.1f} s")
+    net = GuessNet(seed=0)
+    if a.state_in:
+        with np.load(a.state_in) as st:
+            net.load({k: st[k] for k in st.files})
+    t2 = time.time()
+    hist = net.train(X, T, M, epochs=a.epochs, seed=a.stream_part, log=log)
+    torch.cuda.synchronize()
+    np.savez(os.path.join(a.out, "guess_state.npz"), **net.state(full=True))
+    rec = {"part": a.stream_part, "parts": a.stream_parts, "molecules": [lo, hi],
+           "converged": len(mols), "samples": int(X.shape[0]), "scf_seconds": t_scf,
+           "feature_seconds": t_feat, "train_seconds": time.time() - t2, "loss": hist,
+           "adam_step": net.step, "conv_rms_dD": a.conv}
+    with open(os.path.join(a.out, f"guess_part{a.stream_part}.json"), "w") as f:
+        json.dump(rec, f, indent=1)
+    log(f"part done: {json.dumps({k: v for k, v in rec.items() if k != 'loss'})}")
 
 
 def main():
@@ -571,9 +663,20 @@ def main():
                     help="evaluate saved weights (guess_weights.npz) instead of training")
     ap.add_argument("--eval-offset", type=int, default=0,
                     help="first held-out cluster index (seed 6_000_000 + index)")
+    ap.add_argument("--stream-part", type=int, default=None,
+                    help="train on part K of the --total training set (continuing from "
+                         "--state-in) and save the full training state")
+    ap.add_argument("--stream-parts", type=int, default=4)
+    ap.add_argument("--total", type=int, default=20000)
+    ap.add_argument("--state-in", default=None)
+    ap.add_argument("--conv", type=float, default=1e-5,
+                    help="RMS density change that ends a training SCF (streaming)")
+    ap.add_argument("--workers", type=int, default=8)
     a = ap.parse_args()
     os.makedirs(a.out, exist_ok=True)
     log = lambda s: print(f"[guess] {s}", flush=True)
+    if a.stream_part is not None:
+        return stream_part(a, log)
     if a.weights:
         net = GuessNet(seed=0)
         with np.load(a.weights) as st:

@@ -583,6 +583,80 @@ def test_batch_jk_matches_oracle_per_molecule():
         assert np.max(np.abs(Ks[k].cpu().numpy() - Ko)) < 1e-11, k
 
 
+@pytest.mark.parametrize("persistent", [False, True])
+def test_persistent_launch_matches_oracle(persistent):
+    """The s/p classes in one persistent queue launch (or per class): a small
+    batch of C/H molecules, a water molecule and an H chain, FP64 and with
+    every quartet an FP32 tile, J and K per molecule against the oracle; and
+    a water trimer, whose d classes keep their own launches."""
+    mols = _small_batch()
+    for tf32, tol in ((0.0, 1e-11), (1e6, None)):
+        bt = _fsim().Batch(mols, tau_fp32=tf32)
+        bt.set_persistent(persistent)
+        bt.schwarz_screen(tau=0.0)
+        blocks = [_random_density(synth.nbf_of(b), 40 + k) for k, b in enumerate(mols)]
+        r = bt.fock_build(bt.pack([_dev(x) for x in blocks]),
+                          precision="mixed" if tf32 else "fp64", want_jk=True)
+        Js, Ks = bt.unpack(r["J"]), bt.unpack(r["K"])
+        for k, b in enumerate(mols):
+            Jo, Ko = oracle.Basis(b).fock_jk(blocks[k], tau=0.0)
+            tj = tol if tol else 1e-6 * max(1.0, np.max(np.abs(Jo)))
+            tk = tol if tol else 1e-6 * max(1.0, np.max(np.abs(Ko)))
+            assert np.max(np.abs(Js[k].cpu().numpy() - Jo)) < tj, (k, tf32)
+            assert np.max(np.abs(Ks[k].cpu().numpy() - Ko)) < tk, (k, tf32)
+    b = synth.water_cluster(3, 2)
+    ctx = _ctx(b, tau=1e-10)
+    ctx.set_persistent(persistent)
+    ctx.schwarz_screen()
+    D = _random_density(ctx.nbf, 8)
+    Jo, Ko = oracle.Basis(b).fock_jk(D, tau=1e-10)
+    ctx.set_profiling(True)
+    r = ctx.fock_build(_dev(D), want_jk=True)
+    prof = ctx.class_profile()
+    ctx.set_profiling(False)
+    assert np.max(np.abs(r["J"].cpu().numpy() - Jo)) < 1e-11
+    assert np.max(np.abs(r["K"].cpu().numpy() - Ko)) < 1e-11
+    persist_recs = [p for p in prof if p["bra_class"] == 6]
+    assert len(persist_recs) == (1 if persistent else 0)
+    if persistent:
+        assert all(p["bra_class"] >= 3 for p in prof if p["bra_class"] != 6)
+
+
+def test_ch1024_persistent_graph_one_launch():
+    """ch1024 in its benchmark configuration with the persistent launch: one
+    ERI launch per build and precision (C/H molecules have no d shells), the
+    captured graph replays to the eager result, and the energies equal the
+    per-class build's."""
+    from paper_2510_24968_amd import autotune
+    mols, w = synth.workload("ch1024")
+    bt = _fsim().Batch(mols, tau=w["tau"], tau_fp32=w["tau_fp32"])
+    bt.schwarz_screen()
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    autotune.apply(bt, autotune.load(os.path.join(root, "paper_2510_24968_amd", "tuning",
+                                                   "ch1024_mi355x.json")))
+    D = bt.core_guess()
+    ref = {p: bt.fock_build(D, p)["F"].clone() for p in ("fp64", "mixed")}
+    Eref = bt.energies()
+    bt.set_persistent(True)
+    bt.set_profiling(True)
+    for p in ("fp64", "mixed"):
+        F = bt.fock_build(D, p, energy=False)["F"]
+        prof = bt.class_profile()
+        assert len(prof) == (1 if p == "fp64" else 2) and all(r["bra_class"] == 6 for r in prof)
+        print(f"ch1024 persistent {p}: {[round(r['ms'], 2) for r in prof]} ms, "
+              f"max |dF| = {torch.max(torch.abs(F - ref[p])).item():.2e}", flush=True)
+        assert torch.max(torch.abs(F - ref[p])).item() < 1e-10
+    bt.set_profiling(False)
+    bt.set_graph(True)
+    for rep in range(3):
+        F = bt.fock_build(D, "fp64")["F"]
+        torch.cuda.synchronize()
+        assert torch.max(torch.abs(F - ref["fp64"])).item() < 1e-10, rep
+        _ = (D * 2.0).sum().item()
+    bt.fock_build(D, "fp64")
+    assert np.max(np.abs(bt.energies() - Eref)) < 1e-9
+
+
 def test_ch1024_bench_configuration_stratified_molecules():
     """The 1024-molecule batch in the configuration its benchmark times
     (committed tuning cache, FP64 and mixed, graph-replayed builds): 16

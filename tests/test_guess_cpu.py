@@ -237,3 +237,35 @@ def test_oracle_mcweeny_fixed_point_and_quadratic_convergence():
         assert c < 10 * a * a + 1e-13          # quadratic
     DN = oracle.mcweeny(Dp, S, 6)[0]
     assert abs(np.trace(DN @ S) - b["nelec"]) < 1e-8
+
+
+def test_training_set_interleaves_chains_and_clusters():
+    """The configured training population: even indices H chains (even atom
+    counts 4..32), odd indices water clusters (2..16 molecules), seeds
+    5,000,000 + i, the same molecules however the list is sliced."""
+    from paper_2510_24968_amd import guess
+    mols = guess.training_set(40)
+    assert len(mols) == 40
+    for i, b in enumerate(mols):
+        if i % 2 == 0:
+            assert b["name"].startswith("H") and len(b["Z"]) % 2 == 0 and 4 <= len(b["Z"]) <= 32
+        else:
+            assert b["name"].startswith("(H2O)") and 2 <= len(b["Z"]) // 3 <= 16
+            assert b["name"].endswith(f"seed{5_000_000 + i}")
+    again = guess.training_set(40)
+    assert all(np.array_equal(a["xyz"], b["xyz"]) for a, b in zip(mols, again))
+
+
+def test_dataset_pool_equals_serial():
+    from paper_2510_24968_amd import guess
+    mols = guess.training_set(6)
+    rng = np.random.default_rng(0)
+    dens = []
+    for b in mols:
+        n = synth.nbf_of(b)
+        A = rng.standard_normal((n, n))
+        dens.append(0.5 * (A + A.T))
+    serial = guess.dataset(mols, dens, workers=1)
+    pooled = guess.dataset(mols, dens, workers=3)
+    for x, y in zip(serial, pooled):
+        assert np.array_equal(x, y)

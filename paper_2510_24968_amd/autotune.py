@@ -19,12 +19,15 @@ def cache_key(rec):
     return f"{rec['cls']}|{prec}|K{rec['kbra']}x{rec['kket']}"
 
 
-def tune(ctx, D, precisions=("mixed", "fp64")):
+def tune(ctx, D, precisions=("mixed", "fp64"), progress=True):
     """Run the search for each precision; returns {key: record}.  FP32
     settings come from the mixed build and FP64 settings from the FP64
     build (whose FP64 lists hold every kept quartet, not only the mixed
     build's FP64 part); the context ends with the combined settings."""
     table = {}
+    if progress:
+        # one line per timed pass from the library (see fsim_autotune)
+        os.environ["FSIM_AUTOTUNE_VERBOSE"] = "1"
     for prec in precisions:
         print(f"[autotune] {prec}: searching variants x waves-per-block", file=sys.stderr,
               flush=True)

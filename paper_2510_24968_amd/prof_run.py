@@ -20,6 +20,10 @@ def main():
     ap.add_argument("--workload", default="water64")
     ap.add_argument("--precision", default="fp64", choices=("fp64", "mixed"))
     ap.add_argument("--builds", type=int, default=1)
+    ap.add_argument("--density", default="diag", choices=("diag", "core"),
+                    help="diag: 0.01 I (the build evaluates every kept quartet whatever the "
+                         "density, so the kernels' work is the same and no eigensolver "
+                         "dispatches run under the counters); core: the core-Hamiltonian guess")
     a = ap.parse_args()
     import torch
     import synth
@@ -33,13 +37,21 @@ def main():
     log(f"calibration copy of {COPY_BYTES} bytes done")
     del src, dst
     basis, w = synth.workload(a.workload)
+    log("context (pair tables, one-electron matrices, orthogonaliser)")
     ctx = fsim.Context(basis, tau=w["tau"], tau_fp32=w["tau_fp32"] if w["tau_fp32"] > 0 else 1e-5)
+    log("Schwarz screen")
     ctx.schwarz_screen()
     path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuning",
                         f"{a.workload}_mi355x.json")
     if os.path.exists(path):
         log(f"applied {autotune.apply(ctx, autotune.load(path))} tuned class settings")
-    D = ctx.core_guess()
+    if a.density == "core":
+        log("core-Hamiltonian guess (rocSOLVER dsyevd)")
+        D = ctx.core_guess()
+    else:
+        D = 0.01 * torch.eye(ctx.nbf, dtype=torch.float64, device="cuda")
+    torch.cuda.synchronize()
+    log(f"density ready ({a.density}); Fock builds follow")
     for k in range(a.builds):
         t0 = time.time()
         ctx.fock_build(D, a.precision, energy=False)

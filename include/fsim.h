@@ -282,7 +282,11 @@ fsim_status fsim_get_class_profile(fsim_ctx *ctx, fsim_class_profile *out, int32
  * the primitive loops in ket-outer order (ss, ps, pp and ds bra pairs; other
  * classes run variant 1), variant 5 the one-lane-per-quartet kernel at a
  * budget of 192 live values for classes whose chunks do not fit 160 (others
- * run variant 2).  waves_per_block is 1, 2 or 4. */
+ * run variant 2), variant 6 the one-wave-per-quartet kernel whose two
+ * Hermite contraction steps run as dense products on the matrix cores
+ * (16x16x4 FP64 / FP32 MFMA; classes with a d bra pair, others run variant
+ * 3).  waves_per_block is 1, 2 or 4 (variants 3, 5 and 6 use one block
+ * shape). */
 typedef struct {
     int32_t bra_class, ket_class;   /* pair classes, bra >= ket */
     int32_t fp32;
@@ -302,7 +306,10 @@ fsim_status fsim_get_tuning(fsim_ctx *ctx, fsim_tuning *out, int32_t cap, int32_
 /* Autotuner: time every variant x waves-per-block setting of every class
  * with work, by per-launch HIP events over Fock builds at the density D
  * (device, N x N) in precision prec on stream, and keep the fastest per
- * class.  Needs a screen first.  Synchronises the stream. */
+ * class.  Needs a screen first.  Synchronises the stream.  With the
+ * environment variable FSIM_AUTOTUNE_VERBOSE=1 each timed pass prints one
+ * progress line (precision, variant, waves per block, summed kernel time)
+ * on stderr. */
 fsim_status fsim_autotune(fsim_ctx *ctx, const double *D, fsim_precision prec, void *stream);
 
 /* Contracted ERI blocks (Eq. twoe-final summed over primitives) for n shell

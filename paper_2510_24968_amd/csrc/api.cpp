@@ -8,6 +8,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <numeric>
@@ -1814,7 +1815,7 @@ extern "C" fsim_status fsim_set_tuning(fsim_ctx *c, const fsim_tuning *t, int32_
             r.ket_class > r.bra_class || (r.fp32 != 0 && r.fp32 != 1))
             return fail(FSIM_EINVAL, "tuning record names no quartet class");
         if (r.variant < 0 || r.variant >= ERI_NVARIANT)
-            return fail(FSIM_EINVAL, "variant must be 0..5");
+            return fail(FSIM_EINVAL, "variant must be 0.." + std::to_string(ERI_NVARIANT - 1));
         if (r.waves_per_block != 1 && r.waves_per_block != 2 && r.waves_per_block != 4)
             return fail(FSIM_EINVAL, "waves_per_block must be 1, 2 or 4");
     }
@@ -1886,18 +1887,22 @@ extern "C" fsim_status fsim_autotune(fsim_ctx *c, const double *D, fsim_precisio
             }
     const int wpbs[3] = {1, 2, 4};
     fsim_status st = FSIM_OK;
+    // FSIM_AUTOTUNE_VERBOSE=1: one progress line per timed pass on stderr
+    const char *vb = std::getenv("FSIM_AUTOTUNE_VERBOSE");
+    const bool verbose = vb && vb[0] == '1';
     // one warm-up build
     st = fock_build(c, D, c->F, nullptr, nullptr, nullptr, prec, s);
     for (int v = 0; v < ERI_NVARIANT && st == FSIM_OK; ++v)
         for (int w = 0; w < 3 && st == FSIM_OK; ++w) {
-            if ((v == ERI_VARIANT_WAVE || v == ERI_VARIANT_WIDE) && w > 0) continue;   // one block shape
+            if ((v == ERI_VARIANT_WAVE || v == ERI_VARIANT_WIDE || v == ERI_VARIANT_MFMA) && w > 0)
+                continue;   // one block shape
             // the wave kernel is only a candidate for the high angular-momentum
             // classes (L >= 5) and the ket-outer kernel only for the ss, ps, pp
             // and ds bras;
             // elsewhere those classes keep a lane variant during that pass and
             // are not scored in it
             const bool wave = v == ERI_VARIANT_WAVE, ko = v == ERI_VARIANT_KO,
-                       wide = v == ERI_VARIANT_WIDE;
+                       wide = v == ERI_VARIANT_WIDE, mf = v == ERI_VARIANT_MFMA;
             auto Ltot = [](int X, int Y) {
                 return pclass_l1(X) + pclass_l2(X) + pclass_l1(Y) + pclass_l2(Y);
             };
@@ -1905,16 +1910,24 @@ extern "C" fsim_status fsim_autotune(fsim_ctx *c, const double *D, fsim_precisio
                 for (int Y = 0; Y < NPCLASS; ++Y)
                     for (int f = 0; f < 2; ++f) {
                         const bool cand = (!wave || Ltot(X, Y) >= 5) && (!ko || X <= 3) &&
-                                          (!wide || Ltot(X, Y) >= 7);
+                                          (!wide || Ltot(X, Y) >= 7) && (!mf || X >= 3);
                         c->variant[X][Y][f] = cand ? v : ERI_DEFAULT_VARIANT;
                         c->wpb[X][Y][f] = wpbs[w];
                     }
             st = fock_build(c, D, c->F, nullptr, nullptr, nullptr, prec, s);
             if (st != FSIM_OK) break;
+            if (verbose) {
+                double tot = 0.0;
+                for (const auto &r : c->prof) tot += r.ms;
+                std::fprintf(stderr, "[fsim_autotune] %s variant %d, %d waves/block: %.1f ms\n",
+                             prec == FSIM_MIXED ? "mixed" : "fp64", v, wpbs[w], tot);
+                std::fflush(stderr);
+            }
             for (const auto &r : c->prof)
                 if ((!wave || Ltot(r.bra_class, r.ket_class) >= 5) &&
                     (!ko || r.bra_class <= 3) &&
                     (!wide || Ltot(r.bra_class, r.ket_class) >= 7) &&
+                    (!mf || r.bra_class >= 3) &&
                     r.ms < best[r.bra_class][r.ket_class][r.fp32]) {
                     best[r.bra_class][r.ket_class][r.fp32] = r.ms;
                     bv[r.bra_class][r.ket_class][r.fp32] = v;

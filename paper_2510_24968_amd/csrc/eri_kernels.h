@@ -1072,6 +1072,374 @@ __global__ __launch_bounds__(64) void k_eri_wave(EriArgs a) {
     }
 }
 
+// ===========================================================================
+// Kernel C: one wave per contracted quartet with both E.R.E steps on the
+// matrix cores (16x16x4 MFMA, FP64 or FP32).  Per primitive quartet,
+//   W[h_ab][cd] += sum_{h_cd} R^0[h_ab + h_cd] Et[h_cd][cd]     (step 1)
+// with Et the ket Hermite entries carrying (-1)^{tau+nu+phi} (zero outside a
+// component pair's box); per bra primitive pair,
+//   (ab|cd)     += sum_{h_ab} E[ab][h_ab] W[h_ab][cd]            (step 2).
+// Both are dense products over the Hermite index, the J_{tuv,k} form of
+// Sec. 2.5 (Eq. eri-tensor-contracted) written as matrix products.
+// Operand layout of v_mfma_{f64,f32}_16x16x4 (lane l): A[l % 16][l / 16],
+// B[l / 16][l % 16]; accumulator v of lane l holds D[l / 16 + 4 v][l % 16]
+// for FP64 and D[4 (l / 16) + v][l % 16] for FP32.
+// ===========================================================================
+typedef double mfma_v4d __attribute__((ext_vector_type(4)));
+typedef float mfma_v4f __attribute__((ext_vector_type(4)));
+template <typename T>
+struct MfmaOp;
+template <>
+struct MfmaOp<double> {
+    using acc = mfma_v4d;
+    static __device__ __forceinline__ acc mma(double x, double y, acc c) {
+        return __builtin_amdgcn_mfma_f64_16x16x4f64(x, y, c, 0, 0, 0);
+    }
+    static __device__ __forceinline__ int row(int lane, int v) { return (lane >> 4) + 4 * v; }
+};
+template <>
+struct MfmaOp<float> {
+    using acc = mfma_v4f;
+    static __device__ __forceinline__ acc mma(float x, float y, acc c) {
+        return __builtin_amdgcn_mfma_f32_16x16x4f32(x, y, c, 0, 0, 0);
+    }
+    static __device__ __forceinline__ int row(int lane, int v) { return 4 * (lane >> 4) + v; }
+};
+
+// F_0..F_L at T from the FP64 grid in global memory (wave-uniform reads).
+template <int L>
+__device__ __forceinline__ void boys_eval_global(double T, const double *__restrict__ g, double *F) {
+    if (T < BOYS_TMAX) {
+        const int k = __double2int_rn(T * BOYS_INV_DT);
+        const double d = k * BOYS_DT - T;
+        const double *c = g + k * BOYS_NORD + L;
+        double f = c[BOYS_NTAYLOR - 1] * inv_factorial(BOYS_NTAYLOR - 1);
+#pragma unroll
+        for (int j = BOYS_NTAYLOR - 2; j >= 0; --j) f = fma(f, d, c[j] * inv_factorial(j));
+        F[L] = f;
+        if constexpr (L > 0) {
+            const double e = exp(-T), t2 = 2.0 * T;
+#pragma unroll
+            for (int n = L; n > 0; --n) F[n - 1] = fma(t2, F[n], e) * (1.0 / (2 * n - 1));
+        }
+    } else {
+        F[0] = 0.88622692545275801365 * rsqrt(T);
+        if constexpr (L > 0) {
+            const double e = exp(-T), h = 0.5 / T;
+#pragma unroll
+            for (int n = 0; n < L; ++n) F[n + 1] = ((2 * n + 1) * F[n] - e) * h;
+        }
+    }
+}
+
+template <int LA, int LB, int LC, int LD, typename T, bool STORE>
+__global__ __launch_bounds__(64) void k_eri_mfma(EriArgs a) {
+    constexpr int L = LA + LB + LC + LD, LAB = LA + LB, LCD = LC + LD;
+    constexpr int NA = ncart(LA), NB = ncart(LB), NC = ncart(LC), ND = ncart(LD);
+    constexpr int NAB = NA * NB, NCD = NC * ND;
+    constexpr int NHAB = nherm(LAB), NHCD = nherm(LCD), NH = nherm(L);
+    constexpr int NEB = n_entries(LA, LB), NEK = n_entries(LC, LD);
+    constexpr int MT1 = (NHAB + 15) / 16, NT = (NCD + 15) / 16, KS1 = (NHCD + 3) / 4;
+    constexpr int MT2 = (NAB + 15) / 16, KS2 = (NHAB + 3) / 4;
+    constexpr int KR = KS1 * 4, NC16 = NT * 16, MR2 = MT2 * 16, KR2 = KS2 * 4;
+    constexpr int NO = NAB * NCD, NRL = (NH + 63) / 64;
+    using M = MfmaOp<T>;
+    using acc_t = typename M::acc;
+    // digest staging (as kernel B): density blocks and J'/K' targets
+    constexpr int DO_CD = NAB, DO_BD = DO_CD + NCD, DO_AD = DO_BD + NB * ND,
+                  DO_BC = DO_AD + NA * ND, DO_AC = DO_BC + NB * NC, NDEN = DO_AC + NA * NC;
+    constexpr int TG_JCD = NAB, TG_KAC = TG_JCD + NCD, TG_KBC = TG_KAC + NA * NC,
+                  TG_KAD = TG_KBC + NB * NC, TG_KBD = TG_KAD + NA * ND, NTGT = TG_KBD + NB * ND;
+    constexpr int NWST = (KR2 * NC16 * (int)sizeof(T) + 7) / 8;   // W staging, in doubles
+    constexpr int NU = STORE ? NWST : (NWST > NO ? NWST : NO);
+    __shared__ T rbuf[2][NH];
+    __shared__ T ekl[NEK], ebl[NEB];
+    constexpr int MR1 = MT1 * 16;
+    __shared__ short rmap[MR1][KR];    // R^0 index of (h_ab, h_cd), -1 in the padding
+    __shared__ short kmap[KR][NC16];   // +-(ket entry + 1) with the Hermite sign, 0 outside
+    __shared__ short bmap[MR2][KR2];   // bra entry + 1, 0 outside
+    __shared__ double ubuf[NU];        // W staging, then the scaled block for the digest
+    __shared__ double den[STORE ? 1 : NDEN];
+    T *wst = (T *)ubuf;
+    const int lane = threadIdx.x;
+
+    for (int x = lane; x < KR * NC16; x += 64) {
+        const int k = x / NC16, n = x % NC16;
+        int val = 0;
+        if (k < NHCD && n < NCD) {
+            const int t = hidx_t(k), u = hidx_u(k), v = hidx_v(k);
+            const int bx = box_dim(LC, LD, n, 0), by = box_dim(LC, LD, n, 1),
+                      bz = box_dim(LC, LD, n, 2);
+            if (t <= bx && u <= by && v <= bz) {
+                const int e = box_off(LC, LD, n) + (t * (by + 1) + u) * (bz + 1) + v;
+                val = ((t + u + v) & 1) ? -(e + 1) : e + 1;
+            }
+        }
+        kmap[k][n] = (short)val;
+    }
+    for (int x = lane; x < MR2 * KR2; x += 64) {
+        const int m = x / KR2, k = x % KR2;
+        int val = 0;
+        if (m < NAB && k < NHAB) {
+            const int t = hidx_t(k), u = hidx_u(k), v = hidx_v(k);
+            const int bx = box_dim(LA, LB, m, 0), by = box_dim(LA, LB, m, 1),
+                      bz = box_dim(LA, LB, m, 2);
+            if (t <= bx && u <= by && v <= bz)
+                val = box_off(LA, LB, m) + (t * (by + 1) + u) * (bz + 1) + v + 1;
+        }
+        bmap[m][k] = (short)val;
+    }
+    for (int x = lane; x < MR1 * KR; x += 64) {
+        const int r = x / KR, k = x % KR;
+        rmap[r][k] = (short)((r < NHAB && k < NHCD)
+                                 ? hidx(hidx_t(r) + hidx_t(k), hidx_u(r) + hidx_u(k),
+                                        hidx_v(r) + hidx_v(k))
+                                 : -1);
+    }
+    // level decode of the R recursion (as kernel B)
+    int rt[NRL], ru[NRL], rv[NRL];
+#pragma unroll
+    for (int k = 0; k < NRL; ++k) {
+        const int id = lane + 64 * k < NH ? lane + 64 * k : 0;
+        rt[k] = hidx_t(id);
+        ru[k] = hidx_u(id);
+        rv[k] = hidx_v(id);
+    }
+    __syncthreads();
+
+    const int ntile = STORE ? a.st_ntile : a.tl.ntile;
+    const T *__restrict__ Eb = etab<T>(a.bra);
+    const T *__restrict__ Ek = etab<T>(a.ket);
+    const size_t nb = a.bra.n, nk = a.ket.n;
+
+    for (int tile = blockIdx.x; tile < ntile; tile += gridDim.x) {
+        int bra, k0 = 0, k1 = 0;
+        if constexpr (STORE) {
+            bra = a.st_bra[tile];
+            k1 = 64;
+        } else {
+            const int b = tile_bra(a.tl, tile);
+            bra = a.tl.bra[b];
+            k0 = a.tl.ket_lo[b] + (tile - a.tl.tile_start[b]) * TILE;
+            k1 = min(k0 + TILE, a.tl.ket_hi[b]);
+        }
+        const int nbp = a.bra.nprim[bra];
+        for (int kk = k0; kk < k1; ++kk) {
+            int ket = kk;
+            if constexpr (STORE) {
+                ket = a.st_ket[tile * 64 + kk];
+                if (ket < 0) continue;
+            }
+            const int nkp = a.ket.nprim[ket];
+            acc_t o[MT2][NT];
+#pragma unroll
+            for (int mt = 0; mt < MT2; ++mt)
+#pragma unroll
+                for (int nt = 0; nt < NT; ++nt) o[mt][nt] = acc_t{};
+            for (int i = 0; i < nbp; ++i) {
+                const double p = a.bra.p[i * nb + bra];
+                const double Px = a.bra.P[(i * 3 + 0) * nb + bra];
+                const double Py = a.bra.P[(i * 3 + 1) * nb + bra];
+                const double Pz = a.bra.P[(i * 3 + 2) * nb + bra];
+                for (int e = lane; e < NEB; e += 64) ebl[e] = Eb[((size_t)i * NEB + e) * nb + bra];
+                acc_t w[MT1][NT];
+#pragma unroll
+                for (int mt = 0; mt < MT1; ++mt)
+#pragma unroll
+                    for (int nt = 0; nt < NT; ++nt) w[mt][nt] = acc_t{};
+                for (int j = 0; j < nkp; ++j) {
+                    const double q = a.ket.p[j * nk + ket];
+                    const double X = Px - a.ket.P[(j * 3 + 0) * nk + ket];
+                    const double Y = Py - a.ket.P[(j * 3 + 1) * nk + ket];
+                    const double Z = Pz - a.ket.P[(j * 3 + 2) * nk + ket];
+                    const double pq = p + q, alpha = p * q / pq;
+                    double F[L + 1];
+                    boys_eval_global<L>(alpha * (X * X + Y * Y + Z * Z), a.boys, F);
+                    T src[L + 1];
+                    double m = 1.0 / sqrt(pq);
+#pragma unroll
+                    for (int n = 0; n <= L; ++n) {
+                        src[n] = T(F[n] * m);
+                        m *= -2.0 * alpha;
+                    }
+                    for (int e = lane; e < NEK; e += 64)
+                        ekl[e] = Ek[((size_t)j * NEK + e) * nk + ket];
+                    // R^0 level by level (level n holds totals <= L - n)
+                    int cur = 0;
+                    if (lane == 0) rbuf[0][0] = src[L];
+                    __syncthreads();
+                    for (int n = L - 1; n >= 0; --n) {
+                        const int nxt = cur ^ 1, cnt = nherm(L - n);
+                        const T Xt = T(X), Yt = T(Y), Zt = T(Z);
+#pragma unroll
+                        for (int k = 0; k < NRL; ++k) {
+                            const int id = lane + 64 * k;
+                            if (id < cnt) {
+                                const int t = rt[k], u = ru[k], v = rv[k];
+                                T val;
+                                if (id == 0) val = src[n];
+                                else if (t > 0)
+                                    val = Xt * rbuf[cur][hidx(t - 1, u, v)] +
+                                          (t > 1 ? T(t - 1) * rbuf[cur][hidx(t - 2, u, v)] : T(0));
+                                else if (u > 0)
+                                    val = Yt * rbuf[cur][hidx(t, u - 1, v)] +
+                                          (u > 1 ? T(u - 1) * rbuf[cur][hidx(t, u - 2, v)] : T(0));
+                                else
+                                    val = Zt * rbuf[cur][hidx(t, u, v - 1)] +
+                                          (v > 1 ? T(v - 1) * rbuf[cur][hidx(t, u, v - 2)] : T(0));
+                                rbuf[nxt][id] = val;
+                            }
+                        }
+                        cur = nxt;
+                        __syncthreads();
+                    }
+                    const T *R = rbuf[cur];
+                    // step 1 on the matrix cores (K steps not unrolled: the
+                    // operands of one step are loaded just before its MFMAs)
+#pragma unroll 1
+                    for (int ks = 0; ks < KS1; ++ks) {
+                        T bv[NT];
+#pragma unroll
+                        for (int nt = 0; nt < NT; ++nt) {
+                            const int mk = kmap[4 * ks + (lane >> 4)][16 * nt + (lane & 15)];
+                            bv[nt] = mk == 0 ? T(0) : (mk > 0 ? ekl[mk - 1] : -ekl[-mk - 1]);
+                        }
+#pragma unroll
+                        for (int mt = 0; mt < MT1; ++mt) {
+                            const int ri = rmap[16 * mt + (lane & 15)][4 * ks + (lane >> 4)];
+                            const T av = ri >= 0 ? R[ri] : T(0);
+#pragma unroll
+                            for (int nt = 0; nt < NT; ++nt) w[mt][nt] = M::mma(av, bv[nt], w[mt][nt]);
+                        }
+                    }
+                    __syncthreads();   // rbuf and ekl are rewritten by the next ket primitive
+                }
+                // W to LDS in the B-operand order of step 2 (rows h_ab < KR2)
+#pragma unroll
+                for (int mt = 0; mt < MT1; ++mt)
+#pragma unroll
+                    for (int nt = 0; nt < NT; ++nt)
+#pragma unroll
+                        for (int v = 0; v < 4; ++v) {
+                            const int r = 16 * mt + M::row(lane, v);
+                            if (r < KR2) wst[r * NC16 + 16 * nt + (lane & 15)] = w[mt][nt][v];
+                        }
+                __syncthreads();
+                // step 2 on the matrix cores
+#pragma unroll 1
+                for (int ks = 0; ks < KS2; ++ks) {
+                    T bv[NT];
+#pragma unroll
+                    for (int nt = 0; nt < NT; ++nt)
+                        bv[nt] = wst[(4 * ks + (lane >> 4)) * NC16 + 16 * nt + (lane & 15)];
+#pragma unroll
+                    for (int mt = 0; mt < MT2; ++mt) {
+                        const int mb = bmap[16 * mt + (lane & 15)][4 * ks + (lane >> 4)];
+                        const T av = mb ? ebl[mb - 1] : T(0);
+#pragma unroll
+                        for (int nt = 0; nt < NT; ++nt) o[mt][nt] = M::mma(av, bv[nt], o[mt][nt]);
+                    }
+                }
+                __syncthreads();   // wst and ebl are rewritten by the next bra primitive
+            }
+            if constexpr (STORE) {
+                const size_t qq = (size_t)tile * 64 + kk;
+                const long long off = a.st_off[qq];
+                const int s0 = a.st_stride[qq * 4 + 0], s1 = a.st_stride[qq * 4 + 1],
+                          s2 = a.st_stride[qq * 4 + 2], s3 = a.st_stride[qq * 4 + 3];
+#pragma unroll
+                for (int mt = 0; mt < MT2; ++mt)
+#pragma unroll
+                    for (int nt = 0; nt < NT; ++nt)
+#pragma unroll
+                        for (int v = 0; v < 4; ++v) {
+                            const int ab = 16 * mt + M::row(lane, v), cd = 16 * nt + (lane & 15);
+                            if (ab < NAB && cd < NCD)
+                                a.out[off + (ab / NB) * s0 + (ab % NB) * s1 + (cd / ND) * s2 +
+                                      (cd % ND) * s3] = (double)o[mt][nt][v];
+                        }
+            } else {
+                const int mol = a.bra.mol[bra];
+                const long long mbase = a.mol_off[mol];
+                const int N = a.mol_n[mol];
+                const double *__restrict__ D = a.D + mbase;
+                const long long xoff = a.xcd_stride ? xcd_index() * a.xcd_stride : 0;
+                double *__restrict__ Jh = a.Jh + xoff + mbase;
+                double *__restrict__ Kh = a.Kh + xoff + mbase;
+                const int f1 = a.bra.bf1[bra], f2 = a.bra.bf2[bra];
+                const int f3 = a.ket.bf1[ket], f4 = a.ket.bf2[ket];
+                double fac = 1.0;
+                if (a.bra.sh1[bra] == a.bra.sh2[bra]) fac *= 0.5;
+                if (a.ket.sh1[ket] == a.ket.sh2[ket]) fac *= 0.5;
+                if (a.same_class && ket == bra) fac *= 0.5;
+                double *blk = ubuf;
+#pragma unroll
+                for (int mt = 0; mt < MT2; ++mt)
+#pragma unroll
+                    for (int nt = 0; nt < NT; ++nt)
+#pragma unroll
+                        for (int v = 0; v < 4; ++v) {
+                            const int ab = 16 * mt + M::row(lane, v), cd = 16 * nt + (lane & 15);
+                            if (ab < NAB && cd < NCD) blk[ab * NCD + cd] = fac * (double)o[mt][nt][v];
+                        }
+                for (int x = lane; x < NDEN; x += 64) {
+                    size_t r, c;
+                    if (x < DO_CD) { r = f1 + x / NB; c = f2 + x % NB; }
+                    else if (x < DO_BD) { r = f3 + (x - DO_CD) / ND; c = f4 + (x - DO_CD) % ND; }
+                    else if (x < DO_AD) { r = f2 + (x - DO_BD) / ND; c = f4 + (x - DO_BD) % ND; }
+                    else if (x < DO_BC) { r = f1 + (x - DO_AD) / ND; c = f4 + (x - DO_AD) % ND; }
+                    else if (x < DO_AC) { r = f2 + (x - DO_BC) / NC; c = f3 + (x - DO_BC) % NC; }
+                    else { r = f1 + (x - DO_AC) / NC; c = f3 + (x - DO_AC) % NC; }
+                    den[x] = D[r * N + c];
+                }
+                __syncthreads();
+                for (int t = lane; t < NTGT; t += 64) {
+                    double sum = 0.0;
+                    if (t < TG_JCD) {   // J'_ab += 2 sum_cd v D_cd
+#pragma unroll 2
+                        for (int cd = 0; cd < NCD; ++cd) sum += blk[t * NCD + cd] * den[DO_CD + cd];
+                        atomicAdd(&Jh[(size_t)(f1 + t / NB) * N + f2 + t % NB], 2.0 * sum);
+                    } else if (t < TG_KAC) {   // J'_cd += 2 sum_ab v D_ab
+                        const int cd = t - TG_JCD;
+#pragma unroll 2
+                        for (int ab = 0; ab < NAB; ++ab) sum += blk[ab * NCD + cd] * den[ab];
+                        atomicAdd(&Jh[(size_t)(f3 + cd / ND) * N + f4 + cd % ND], 2.0 * sum);
+                    } else if (t < TG_KBC) {   // K'_ac += sum_bd v D_bd
+                        const int ia = (t - TG_KAC) / NC, ic = (t - TG_KAC) % NC;
+#pragma unroll 1
+                        for (int ib = 0; ib < NB; ++ib)
+                            for (int id = 0; id < ND; ++id)
+                                sum += blk[(ia * NB + ib) * NCD + ic * ND + id] * den[DO_BD + ib * ND + id];
+                        atomicAdd(&Kh[(size_t)(f1 + ia) * N + f3 + ic], sum);
+                    } else if (t < TG_KAD) {   // K'_bc += sum_ad v D_ad
+                        const int ib = (t - TG_KBC) / NC, ic = (t - TG_KBC) % NC;
+#pragma unroll 1
+                        for (int ia = 0; ia < NA; ++ia)
+                            for (int id = 0; id < ND; ++id)
+                                sum += blk[(ia * NB + ib) * NCD + ic * ND + id] * den[DO_AD + ia * ND + id];
+                        atomicAdd(&Kh[(size_t)(f2 + ib) * N + f3 + ic], sum);
+                    } else if (t < TG_KBD) {   // K'_ad += sum_bc v D_bc
+                        const int ia = (t - TG_KAD) / ND, id = (t - TG_KAD) % ND;
+#pragma unroll 1
+                        for (int ib = 0; ib < NB; ++ib)
+                            for (int ic = 0; ic < NC; ++ic)
+                                sum += blk[(ia * NB + ib) * NCD + ic * ND + id] * den[DO_BC + ib * NC + ic];
+                        atomicAdd(&Kh[(size_t)(f1 + ia) * N + f4 + id], sum);
+                    } else {   // K'_bd += sum_ac v D_ac
+                        const int ib = (t - TG_KBD) / ND, id = (t - TG_KBD) % ND;
+#pragma unroll 1
+                        for (int ia = 0; ia < NA; ++ia)
+                            for (int ic = 0; ic < NC; ++ic)
+                                sum += blk[(ia * NB + ib) * NCD + ic * ND + id] * den[DO_AC + ia * NC + ic];
+                        atomicAdd(&Kh[(size_t)(f2 + ib) * N + f4 + id], sum);
+                    }
+                }
+                __syncthreads();   // blk and den are rewritten by the next quartet
+            }
+        }
+    }
+}
+
 // Launch variants.  Variants 0..2 fix the per-lane register budget of kernel
 // A (live block + W + R^0 values; the chunking follows from it); variant 3 is
 // kernel B; variant 4 is kernel A in ket-outer order (bras with small
@@ -1079,10 +1447,11 @@ __global__ __launch_bounds__(64) void k_eri_wave(EriArgs a) {
 // fit, or needs more than MAX_CHUNKS chunks, falls back to kernel B.  The
 // autotuner picks a variant and the waves per block for every class and
 // precision.
-constexpr int NVARIANT = 6;
+constexpr int NVARIANT = 7;
 constexpr int VARIANT_WAVE = 3;
 constexpr int VARIANT_KO = 4;
 constexpr int VARIANT_WIDE = 5;   // kernel A at 192 live values, where 160 does not fit
+constexpr int VARIANT_MFMA = 6;   // kernel C (matrix cores), classes with a d bra
 constexpr int DEFAULT_VARIANT = 1;
 __host__ __device__ constexpr int variant_budget(int v) {
     return v == 0 ? 96 : (v == 1 ? 128 : (v == 2 ? 160 : (v == VARIANT_WIDE ? 192 : 0)));
@@ -1110,6 +1479,13 @@ void launch_wave_kernel(int ntile, const EriArgs &a, hipStream_t s) {
     int blocks = ntile;
     if (blocks > 32768) blocks = 32768;
     hipLaunchKernelGGL((k_eri_wave<LA, LB, LC, LD, T, STORE>), dim3(blocks), dim3(64), 0, s, a);
+}
+
+template <int LA, int LB, int LC, int LD, typename T, bool STORE>
+void launch_mfma_kernel(int ntile, const EriArgs &a, hipStream_t s) {
+    int blocks = ntile;
+    if (blocks > 32768) blocks = 32768;
+    hipLaunchKernelGGL((k_eri_mfma<LA, LB, LC, LD, T, STORE>), dim3(blocks), dim3(64), 0, s, a);
 }
 
 template <int LA, int LB, int LC, int LD, typename T, bool STORE, int BUDGET>
@@ -1168,6 +1544,12 @@ void launch_variant(int ntile, int variant, int wpb, const EriArgs &a, hipStream
                 launch_budget<LA, LB, LC, LD, T, STORE, variant_budget(VARIANT_WIDE)>(ntile, wpb, a, s);
             else
                 launch_budget<LA, LB, LC, LD, T, STORE, variant_budget(2)>(ntile, wpb, a, s);
+            break;
+        case VARIANT_MFMA:
+            // the matrix-core kernel serves classes with a d bra; the others
+            // run the wave kernel
+            if constexpr (LA == 2) launch_mfma_kernel<LA, LB, LC, LD, T, STORE>(ntile, a, s);
+            else launch_wave_kernel<LA, LB, LC, LD, T, STORE>(ntile, a, s);
             break;
         default: launch_wave_kernel<LA, LB, LC, LD, T, STORE>(ntile, a, s); break;
     }

@@ -220,11 +220,13 @@ hipError_t launch_digest_stored(int bra_pc, int ket_pc, int wpb, const EriArgs &
 // quartet-class dispatch (eri_dispatch.hip); bra_pc >= ket_pc
 hipError_t launch_eri(int bra_pc, int ket_pc, bool fp32, bool store, int variant, int wpb,
                       const EriArgs &a, hipStream_t s);
-constexpr int ERI_NVARIANT = 6;   // kernel-A budgets 96/128/160, kernel B, kernel A ket-outer,
-                                  // kernel A at 192 (classes that do not fit 160)
+constexpr int ERI_NVARIANT = 7;   // kernel-A budgets 96/128/160, kernel B, kernel A ket-outer,
+                                  // kernel A at 192 (classes that do not fit 160),
+                                  // kernel C on the matrix cores (d bras)
 constexpr int ERI_VARIANT_WAVE = 3;
 constexpr int ERI_VARIANT_KO = 4;
 constexpr int ERI_VARIANT_WIDE = 5;
+constexpr int ERI_VARIANT_MFMA = 6;
 constexpr int ERI_DEFAULT_VARIANT = 1;
 
 }  // namespace fsim

@@ -73,7 +73,7 @@ class _Tuning(ctypes.Structure):
 
 
 PAIR_CLASS = ("ss", "ps", "pp", "ds", "dp", "dd", "sp*")   # "sp*": the persistent s/p launch
-NVARIANT = 6
+NVARIANT = 7
 
 
 def _struct_dict(s):

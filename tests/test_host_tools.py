@@ -99,7 +99,7 @@ def test_committed_tuning_caches_are_well_formed():
         assert entries
         for key, e in entries.items():
             assert key == autotune.cache_key(e)
-            assert 0 <= e["variant"] < 6 and e["waves_per_block"] in (1, 2, 4)
+            assert 0 <= e["variant"] < 7 and e["waves_per_block"] in (1, 2, 4)
 
 
 def test_cpu_baseline_samples_kept_quartets():

@@ -172,6 +172,30 @@ def run_batch(a, basis_list, w):
         n = autotune.apply(bt, autotune.load(path))
         tuning_src = f"{os.path.relpath(path, ROOT)} ({n} class settings)"
     log(f"tuning: {tuning_src or 'library defaults'}")
+    tau_prim = 1e-4 * w["tau"] if a.tau_prim is None else a.tau_prim
+    all_prims = None
+    if tau_prim > 0:
+        # every primitive pair first: FP64 Fock build at the core guess
+        bt.set_persistent(not a.per_class)
+        Dg = bt.core_guess()
+        bt.fock_build(Dg, "fp64", energy=False)
+        ts = []
+        for _ in range(3):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            bt.fock_build(Dg, "fp64", energy=False)
+            e1.record()
+            torch.cuda.synchronize()
+            ts.append(e0.elapsed_time(e1))
+        all_prims = {"fock_build_s_fp64": sorted(ts)[1] / 1e3,
+                     "prim_quartets": st["prim_quartets_kept"], "prim_pairs": st["prim_pairs_total"]}
+        bt.set_prim_screen(tau_prim)
+        _, st = bt.schwarz_screen()
+        if tuning_src:
+            autotune.apply(bt, autotune.load(path))
+        log(f"every primitive pair: FP64 build {all_prims['fock_build_s_fp64']:.3f} s; "
+            f"primitive-pair screen at {tau_prim:g}: {st['prim_quartets_kept']} of "
+            f"{all_prims['prim_quartets']} primitive quartets")
     # Fock build alone, persistent s/p launch vs one launch per class
     Dg = bt.core_guess()
     launches = {}
@@ -256,7 +280,9 @@ def run_batch(a, basis_list, w):
                    "tau_screen": w["tau"], "tau_fp32": tau32, "quartets_screened": nq,
                    "quartets_canonical": st["quartets_total"], "parallelism": "single GPU",
                    "tuning": tuning_src or "library defaults",
+                   "prim_quartets_screened": st["prim_quartets_kept"], "tau_prim": tau_prim,
                    "eri_launch": "per class" if a.per_class else "persistent s/p queue"},
+        "every_primitive_pair": all_prims,
         "launches": launches,
         "unconverged_note": "energies of molecules that miss the convergence test within 60 "
                             "iterations are unconverged iterates and are left out of the "
@@ -269,6 +295,28 @@ def run_batch(a, basis_list, w):
         "setup_s": t_setup, "screen_s": t_screen,
     }
     print(json.dumps(res), flush=True)
+
+
+def fock_build_times(ctx, a, D):
+    """Median Fock-build seconds per precision at density D (HIP events
+    around each build on the current stream) and E_elec of one more build."""
+    import torch
+    for _ in range(2):
+        ctx.fock_build(D, "fp64", energy=False)
+    fb, E = {}, {}
+    for prec in (["fp64"] if a.no_mixed else ["fp64", "mixed"]):
+        times = []
+        for _ in range(max(3, a.steps)):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            ctx.fock_build(D, prec, energy=False)
+            e1.record()
+            torch.cuda.synchronize()
+            times.append(e0.elapsed_time(e1))
+        times.sort()
+        fb[prec] = times[len(times) // 2] / 1e3
+        E[prec] = ctx.fock_build(D, prec)["E_elec"]
+    return fb, E
 
 
 def main():
@@ -289,6 +337,9 @@ def main():
     ap.add_argument("--tuning", default=None,
                     help="autotuner cache (JSON); default: the committed one for this workload")
     ap.add_argument("--autotune", action="store_true", help="tune in-process before timing")
+    ap.add_argument("--tau-prim", type=float, default=None,
+                    help="primitive-pair screening threshold (default 1e-4 x the Schwarz tau; "
+                         "0: every primitive pair of a kept shell pair)")
     a = ap.parse_args()
     if a.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: the Fock build has no multi-GPU path here; "
@@ -328,6 +379,28 @@ def main():
     log(f"tuning: {tuning_src or 'library defaults'}")
     log(f"nbf={ctx.nbf} setup {t_setup:.2f}s screen {t_screen:.2f}s kept {st['quartets_kept']}"
         f" of {st['quartets_total']} (fp32 part {st['quartets_fp32']})")
+    oracle_ref = stored_oracle_build(a.workload)
+    tau_prim = 1e-4 * w["tau"] if a.tau_prim is None else a.tau_prim
+    all_prims = None
+    if tau_prim > 0:
+        # every primitive pair first: Fock builds at the core-guess density
+        fb0, E0 = fock_build_times(ctx, a, ctx.core_guess())
+        all_prims = {"fock_build_s": fb0,
+                     "quartets_per_s_fp64_build": st["quartets_kept"] / fb0["fp64"],
+                     "prim_quartets": st["prim_quartets_kept"],
+                     "prim_pairs": st["prim_pairs_total"],
+                     "dE_vs_oracle_Ha": {k: (v - oracle_ref["E_elec"]) if oracle_ref else None
+                                         for k, v in E0.items()}}
+        log(f"every primitive pair: Fock build {fb0}")
+        ctx.set_prim_screen(tau_prim)
+        t0 = time.time()
+        _, st = ctx.schwarz_screen()
+        t_screen = time.time() - t0
+        if tuning_src and not a.autotune:
+            autotune.apply(ctx, autotune.load(path))
+        log(f"primitive-pair screen at {tau_prim:g}: {st['prim_pairs_kept']} of "
+            f"{st['prim_pairs_total']} primitive pairs, {st['prim_quartets_kept']} of "
+            f"{all_prims['prim_quartets']} primitive quartets")
 
     def timed_steps(prec, profile=False):
         """K timed SCF steps; with profile, every class launch of every step is
@@ -360,23 +433,7 @@ def main():
         msmx, wallmx, infomx, Dmx, _ = timed_steps("mixed")
     # Fock build alone, and the mixed-vs-FP64 energy difference, at one density
     Dfix = ctx.core_guess()
-    for _ in range(2):
-        ctx.fock_build(Dfix, "fp64", energy=False)
-    fb = {}
-    E = {}
-    for prec in (["fp64"] if a.no_mixed else ["fp64", "mixed"]):
-        times = []
-        for _ in range(max(3, a.steps)):
-            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-            e0.record()
-            ctx.fock_build(Dfix, prec, energy=False)
-            e1.record()
-            torch.cuda.synchronize()
-            times.append(e0.elapsed_time(e1))
-        times.sort()
-        fb[prec] = times[len(times) // 2] / 1e3
-        E[prec] = ctx.fock_build(Dfix, prec)["E_elec"]
-    oracle_ref = stored_oracle_build(a.workload)
+    fb, E = fock_build_times(ctx, a, Dfix)
     # per-class kernel times averaged over the timed FP64 steps
     prof = []
     for rec in steps_prof[0]:
@@ -419,9 +476,11 @@ def main():
                    "tau_screen": w["tau"], "tau_fp32": tau32,
                    "quartets_screened": nq, "quartets_canonical": st["quartets_total"],
                    "prim_quartets_screened": st["prim_quartets_kept"],
+                   "tau_prim": tau_prim,
                    "parallelism": "single GPU",
                    "tuning": tuning_src or "library defaults"},
         "fock_build_s": fb,
+        "every_primitive_pair": all_prims,
         "dE_vs_oracle_Ha": {"fp64": (E["fp64"] - oracle_ref["E_elec"]) if oracle_ref else None,
                             "mixed": (E["mixed"] - oracle_ref["E_elec"])
                             if (oracle_ref and "mixed" in E) else None,

@@ -95,6 +95,8 @@ typedef struct {
                                   one FP64-mode build */
     double flops_mixed_fp64;   /* same, mixed mode, FP64 part */
     double flops_mixed_fp32;   /* same, mixed mode, FP32 part */
+    int64_t prim_pairs_total;  /* primitive pairs of the kept shell pairs */
+    int64_t prim_pairs_kept;   /* of which in use (fewer with fsim_set_prim_screen) */
 } fsim_screen_stats;
 
 typedef struct {
@@ -369,6 +371,22 @@ fsim_status fsim_set_graph(fsim_ctx *ctx, int32_t enable);
  * launch is captured in graphs like the others.  enable = 0 (default):
  * per-class launches with the tuned variants.  Drops captured graphs. */
 fsim_status fsim_set_persistent(fsim_ctx *ctx, int32_t enable);
+
+/* Primitive-pair screening (an addition to the shell-quartet screen of
+ * Sec. 5, which keeps every primitive of a kept shell pair).  For primitive
+ * pair k of a kept shell pair, Q_k = sqrt(max over its component pairs of
+ * (Omega_k|Omega_k)), the self-repulsion of its Hermite distribution (Eq.
+ * twoe-final at zero separation), bounds its part of any integral (ab|cd) by
+ * Q_k Q_cd.  The next fsim_schwarz_screen drops every primitive pair with
+ * Q_k * Q_max < tau_prim (Q_max: the largest shell-pair factor of the
+ * molecule) from the kept pair tables, so each evaluated integral differs
+ * from the unscreened one by at most (primitive pairs dropped from its bra
+ * and ket) * tau_prim.  tau_prim = 0 (default) keeps every primitive pair.
+ * tau_prim must be finite and >= 0 (FSIM_EINVAL).  The call invalidates the
+ * current screen: Fock builds return FSIM_ESTATE until fsim_schwarz_screen
+ * runs again.  The Schwarz factors themselves and fsim_eri_quartets always
+ * use every primitive. */
+fsim_status fsim_set_prim_screen(fsim_ctx *ctx, double tau_prim);
 
 /* Digest target of the Fock build (the J' and K' half-sums of Eq. fock).
  * enable != 0 (the default): every XCD of the GPU adds into its own private

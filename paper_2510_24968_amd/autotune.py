@@ -75,6 +75,9 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--workload", default="water10")
     ap.add_argument("--out", default=None)
+    ap.add_argument("--tau-prim", type=float, default=None,
+                    help="primitive-pair screening threshold to tune under (default 1e-4 x "
+                         "the Schwarz tau, as the benchmark runs; 0: every primitive pair)")
     a = ap.parse_args()
     root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
     sys.path.insert(0, root)
@@ -85,13 +88,16 @@ def main():
         ctx = fsim.Batch(basis, tau=w["tau"], tau_fp32=w["tau_fp32"] or 1e-5)
     else:
         ctx = fsim.Context(basis, tau=w["tau"], tau_fp32=w["tau_fp32"] or 1e-5)
+    tau_prim = 1e-4 * w["tau"] if a.tau_prim is None else a.tau_prim
+    if tau_prim > 0:
+        ctx.set_prim_screen(tau_prim)
     ctx.schwarz_screen()
     D = ctx.core_guess()
     t0 = time.time()
     table = tune(ctx, D)
     print(f"tuned {len(table)} class settings in {time.time() - t0:.1f}s", file=sys.stderr)
     out = a.out or os.path.join(os.getcwd(), f"tuning_{a.workload}.json")
-    save(table, out, {"workload": a.workload, "device": "MI355X (gfx950)"})
+    save(table, out, {"workload": a.workload, "device": "MI355X (gfx950)", "tau_prim": tau_prim})
     print(json.dumps({k: (v["variant"], v["waves_per_block"], round(v["ms"], 3))
                       for k, v in sorted(table.items())}))
 

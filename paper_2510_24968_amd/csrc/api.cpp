@@ -148,6 +148,10 @@ struct fsim_ctx {
     std::vector<double> Qkept[NPCLASS];
     bool screened = false;
     double tau = 0.0, tau32 = 0.0;
+    // primitive-pair screening threshold applied by the next screen (0: off)
+    // and each kept pair's primitive pairs in use after it
+    double tau_prim = 0.0;
+    std::vector<int> kept_np[NPCLASS];
     ClassLists lists[NPCLASS][NPCLASS];
     fsim_screen_stats stats{};
     std::vector<double> Qmat;
@@ -1079,6 +1083,21 @@ extern "C" fsim_status fsim_schwarz_screen(fsim_ctx *c, double tau, double tau32
             HIPCHK(hipMemcpy(c->kept[pc].Q, c->Qkept[pc].data(), sizeof(double) * c->kept[pc].n,
                              hipMemcpyHostToDevice));
         S.pairs_kept += c->kept[pc].n;
+        std::vector<int> &np = c->kept_np[pc];
+        np.resize(s1.size());
+        for (size_t i = 0; i < s1.size(); ++i) np[i] = c->sh_nprim[s1[i]] * c->sh_nprim[s2[i]];
+        for (int v : np) S.prim_pairs_total += v;
+        if (c->tau_prim > 0 && c->kept[pc].n) {
+            double *dq = nullptr;
+            HIPCHK(hipMalloc(&dq, sizeof(double) * c->nmol));
+            HIPCHK(hipMemcpy(dq, Qmax.data(), sizeof(double) * c->nmol, hipMemcpyHostToDevice));
+            HIPCHK(launch_prim_screen(c->kept[pc], dq, c->tau_prim, nullptr));
+            HIPCHK(hipDeviceSynchronize());
+            hipFree(dq);
+            HIPCHK(hipMemcpy(np.data(), c->kept[pc].nprim, sizeof(int) * np.size(),
+                             hipMemcpyDeviceToHost));
+        }
+        for (int v : np) S.prim_pairs_kept += v;
     }
     // canonical quartets: per molecule, npair_m (npair_m + 1) / 2
     {
@@ -1156,11 +1175,8 @@ extern "C" fsim_status fsim_schwarz_screen(fsim_ctx *c, double tau, double tau32
             }
             S.quartets_kept += cl.all64.nquartet;
             // primitive quartets: sum over kept quartets of K_bra * K_ket
-            std::vector<int> kb(Qb.size()), kk(Qk.size());
-            for (size_t i = 0; i < order[X].size(); ++i)
-                kb[i] = c->sh_nprim[c->all_s1[X][order[X][i]]] * c->sh_nprim[c->all_s2[X][order[X][i]]];
-            for (size_t i = 0; i < order[Y].size(); ++i)
-                kk[i] = c->sh_nprim[c->all_s1[Y][order[Y][i]]] * c->sh_nprim[c->all_s2[Y][order[Y][i]]];
+            // (primitive pairs in use: after primitive-pair screening, if on)
+            const std::vector<int> &kb = c->kept_np[X], &kk = c->kept_np[Y];
             std::vector<long long> kpre(kk.size() + 1, 0);
             for (size_t j = 0; j < kk.size(); ++j) kpre[j + 1] = kpre[j] + kk[j];
             cl.s64 = cl.sm64 = cl.sm32 = ListStats{};
@@ -1826,6 +1842,18 @@ extern "C" fsim_status fsim_set_tuning(fsim_ctx *c, const fsim_tuning *t, int32_
         c->tuned_ms[r.bra_class][r.ket_class][r.fp32] = r.ms;
     }
     drop_graphs(c);
+    return FSIM_OK;
+}
+
+extern "C" fsim_status fsim_set_prim_screen(fsim_ctx *c, double tau_prim) {
+    if (!c) return fail(FSIM_EINVAL, "ctx is NULL");
+    if (!(tau_prim >= 0) || !std::isfinite(tau_prim))
+        return fail(FSIM_EINVAL, "tau_prim must be finite and >= 0");
+    c->tau_prim = tau_prim;
+    // the kept tables and work lists are rebuilt by the next screen
+    drop_graphs(c);
+    c->screened = false;
+    c->inc_have = false;
     return FSIM_OK;
 }
 

@@ -191,6 +191,10 @@ struct ShellsDev {
 hipError_t launch_shell_norm(const ShellsDev &sh, hipStream_t s);
 hipError_t launch_build_pairs(const ShellsDev &sh, PairTable &t, const int *pair_sh1,
                               const int *pair_sh2, hipStream_t s);
+// Drop the primitive pairs of every pair whose Schwarz bound times
+// qmax_mol[mol] is below tau_prim, compacting the slots in place (setup.hip).
+hipError_t launch_prim_screen(PairTable &t, const double *qmax_mol, double tau_prim,
+                              hipStream_t s);
 hipError_t launch_one_electron_impl(const ShellsDev &sh, const double *boys, int nmax,
                                     const int *bf_shell, const int *bf_comp, double *S,
                                     double *T, double *V, hipStream_t s);

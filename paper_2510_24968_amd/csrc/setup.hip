@@ -195,6 +195,104 @@ hipError_t launch_build_pairs(const ShellsDev &sh, PairTable &t, const int *ps1,
 }
 
 // ---------------------------------------------------------------------------
+// Primitive-pair screening, one thread per pair.  The Hermite distribution
+// Omega_k of primitive pair k and component pair cp is the sum of the slot's
+// box entries E_tuv times Hermite Gaussians of exponent p at P; by the
+// Cauchy-Schwarz inequality of the Coulomb inner product its part of any
+// integral (ab|cd) is at most sqrt((Omega_k|Omega_k)) Q_cd.  The
+// self-repulsion is Eq. twoe-final with both pairs equal (q = p, R_PQ = 0,
+// alpha = p/2), where R^0_tuv vanishes unless t, u, v are all even and is
+// otherwise (-p)^s (t-1)!! (u-1)!! (v-1)!! / (2s + 1), s = (t + u + v) / 2
+// (the Taylor coefficients of F_0 at zero).  The table's entries carry
+// sqrt(2 pi^(5/2)) / p each, so the sum is scaled by 1 / sqrt(2p) only.
+// Slots whose bound times the molecule's largest shell-pair factor falls
+// below tau_prim are dropped; the kept ones move to the front in their
+// original order and the freed slots become zero padding.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double odd_dfact(int n) {   // (n - 1)!! for even n >= 0
+    double r = 1.0;
+    for (int k = n - 1; k > 1; k -= 2) r *= k;
+    return r;
+}
+
+template <int L1, int L2>
+__global__ void k_prim_screen(PairTable t, const double *__restrict__ qmax_mol, double tau_prim) {
+    constexpr int NCP = ncart(L1) * ncart(L2), NE = n_entries(L1, L2);
+    const int pr = blockIdx.x * blockDim.x + threadIdx.x;
+    if (pr >= t.n) return;
+    const size_t n = t.n;
+    const int np = t.nprim[pr];
+    const double qm = qmax_mol[t.mol[pr]];
+    int kept = 0;
+    for (int k = 0; k < np; ++k) {
+        const double p = t.p[k * n + pr];
+        const double *E = t.E + (size_t)k * NE * n + pr;
+        double q2 = 0.0;
+        for (int cp = 0; cp < NCP; ++cp) {
+            const int bx = box_dim(L1, L2, cp, 0), by = box_dim(L1, L2, cp, 1),
+                      bz = box_dim(L1, L2, cp, 2), eo = box_off(L1, L2, cp);
+            double s = 0.0;
+            for (int t1 = 0; t1 <= bx; ++t1)
+                for (int u1 = 0; u1 <= by; ++u1)
+                    for (int v1 = 0; v1 <= bz; ++v1) {
+                        const double e1 = E[(size_t)(eo + (t1 * (by + 1) + u1) * (bz + 1) + v1) * n];
+                        for (int t2 = t1 & 1; t2 <= bx; t2 += 2)
+                            for (int u2 = u1 & 1; u2 <= by; u2 += 2)
+                                for (int v2 = v1 & 1; v2 <= bz; v2 += 2) {
+                                    const double e2 =
+                                        E[(size_t)(eo + (t2 * (by + 1) + u2) * (bz + 1) + v2) * n];
+                                    const int tt = t1 + t2, uu = u1 + u2, vv = v1 + v2;
+                                    const int sh = (tt + uu + vv) / 2;
+                                    double r = odd_dfact(tt) * odd_dfact(uu) * odd_dfact(vv) /
+                                               (2 * sh + 1);
+                                    for (int m = 0; m < sh; ++m) r *= -p;
+                                    if ((t2 + u2 + v2) & 1) r = -r;
+                                    s += e1 * e2 * r;
+                                }
+                    }
+            q2 = fmax(q2, s);
+        }
+        const double bound = sqrt(fmax(q2, 0.0) * rsqrt(2.0 * p));
+        if (bound * qm >= tau_prim) {
+            if (kept != k) {
+                t.p[kept * n + pr] = p;
+                for (int d = 0; d < 3; ++d) t.P[(kept * 3 + d) * n + pr] = t.P[(k * 3 + d) * n + pr];
+                for (int e = 0; e < NE; ++e) {
+                    t.E[((size_t)kept * NE + e) * n + pr] = t.E[((size_t)k * NE + e) * n + pr];
+                    t.Ef[((size_t)kept * NE + e) * n + pr] = t.Ef[((size_t)k * NE + e) * n + pr];
+                }
+            }
+            ++kept;
+        }
+    }
+    for (int k = kept; k < np; ++k) {
+        t.p[k * n + pr] = 1.0;
+        for (int d = 0; d < 3; ++d) t.P[(k * 3 + d) * n + pr] = 0.0;
+        for (int e = 0; e < NE; ++e) {
+            t.E[((size_t)k * NE + e) * n + pr] = 0.0;
+            t.Ef[((size_t)k * NE + e) * n + pr] = 0.0f;
+        }
+    }
+    t.nprim[pr] = kept;
+}
+
+hipError_t launch_prim_screen(PairTable &t, const double *qmax_mol, double tau_prim,
+                              hipStream_t s) {
+    if (t.n == 0) return hipSuccess;
+    dim3 g((t.n + 127) / 128), b(128);
+    switch (pclass(t.l1, t.l2)) {
+        case 0: hipLaunchKernelGGL((k_prim_screen<0, 0>), g, b, 0, s, t, qmax_mol, tau_prim); break;
+        case 1: hipLaunchKernelGGL((k_prim_screen<1, 0>), g, b, 0, s, t, qmax_mol, tau_prim); break;
+        case 2: hipLaunchKernelGGL((k_prim_screen<1, 1>), g, b, 0, s, t, qmax_mol, tau_prim); break;
+        case 3: hipLaunchKernelGGL((k_prim_screen<2, 0>), g, b, 0, s, t, qmax_mol, tau_prim); break;
+        case 4: hipLaunchKernelGGL((k_prim_screen<2, 1>), g, b, 0, s, t, qmax_mol, tau_prim); break;
+        case 5: hipLaunchKernelGGL((k_prim_screen<2, 2>), g, b, 0, s, t, qmax_mol, tau_prim); break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
 // One-electron matrices, one thread per (mu, nu).
 //   S_ab = E^{ij}_0 E^{kl}_0 E^{mn}_0 (pi/p)^(3/2)                 (Eq. s-overall)
 //   T_ab = sum over directions of

@@ -46,7 +46,8 @@ class _ScreenStats(ctypes.Structure):
                 ("quartets_total", ctypes.c_int64), ("quartets_kept", ctypes.c_int64),
                 ("quartets_fp64", ctypes.c_int64), ("quartets_fp32", ctypes.c_int64),
                 ("prim_quartets_kept", ctypes.c_int64), ("flops_fp64", ctypes.c_double),
-                ("flops_mixed_fp64", ctypes.c_double), ("flops_mixed_fp32", ctypes.c_double)]
+                ("flops_mixed_fp64", ctypes.c_double), ("flops_mixed_fp32", ctypes.c_double),
+                ("prim_pairs_total", ctypes.c_int64), ("prim_pairs_kept", ctypes.c_int64)]
 
 
 class _ScfInfo(ctypes.Structure):
@@ -117,6 +118,7 @@ def lib():
         "fsim_set_graph": [vp, i32],
         "fsim_set_xcd_private": [vp, i32],
         "fsim_set_persistent": [vp, i32],
+        "fsim_set_prim_screen": [vp, dbl],
         "fsim_set_tuning": [vp, vp, i32],
         "fsim_get_tuning": [vp, vp, i32, ctypes.POINTER(i32)],
         "fsim_autotune": [vp, vp, ctypes.c_int, vp],
@@ -184,6 +186,7 @@ class Context:
         self.enuc = e.value
         self.nelec = int(basis["nelec"])
         self.tau, self.tau_fp32 = float(tau), float(tau_fp32)
+        self.tau_prim = 0.0
         self.shell_l = np.asarray(basis["shell_l"], dtype=np.int32)
         self.packed = self.nbf * self.nbf
         self.screen_stats = None
@@ -288,6 +291,13 @@ class Context:
     def set_xcd_private(self, enable=True):
         """Per-XCD private J'/K' accumulators (default on) or one shared copy."""
         _check(lib().fsim_set_xcd_private(self.h, 1 if enable else 0))
+
+    def set_prim_screen(self, tau_prim):
+        """Primitive-pair screening at tau_prim (0: off) for the next
+        schwarz_screen (fsim_set_prim_screen); the current screen is
+        invalidated."""
+        _check(lib().fsim_set_prim_screen(self.h, float(tau_prim)))
+        self.tau_prim = float(tau_prim)
 
     def set_persistent(self, enable=True):
         """s/p quartet classes in one persistent queue launch per precision
@@ -416,6 +426,7 @@ class Batch(Context):
         _check(L.fsim_nbf(self.h, ctypes.byref(n), ctypes.byref(ns)))
         self.nbf, self.nshell = n.value, ns.value
         self.nmol = len(bases)
+        self.tau_prim = 0.0
         nm = ctypes.c_int32()
         self.nbf_mol = np.zeros(self.nmol, dtype=np.int32)
         self.offsets = np.zeros(self.nmol, dtype=np.int64)

@@ -24,6 +24,9 @@ def main():
                     help="diag: 0.01 I (the build evaluates every kept quartet whatever the "
                          "density, so the kernels' work is the same and no eigensolver "
                          "dispatches run under the counters); core: the core-Hamiltonian guess")
+    ap.add_argument("--tau-prim", type=float, default=None,
+                    help="primitive-pair screening threshold (default 1e-4 x the Schwarz tau, "
+                         "as the benchmark runs; 0: every primitive pair)")
     a = ap.parse_args()
     import torch
     import synth
@@ -39,7 +42,10 @@ def main():
     basis, w = synth.workload(a.workload)
     log("context (pair tables, one-electron matrices, orthogonaliser)")
     ctx = fsim.Context(basis, tau=w["tau"], tau_fp32=w["tau_fp32"] if w["tau_fp32"] > 0 else 1e-5)
-    log("Schwarz screen")
+    tau_prim = 1e-4 * w["tau"] if a.tau_prim is None else a.tau_prim
+    if tau_prim > 0:
+        ctx.set_prim_screen(tau_prim)
+    log(f"Schwarz screen (primitive-pair threshold {tau_prim:g})")
     ctx.schwarz_screen()
     path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuning",
                         f"{a.workload}_mi355x.json")

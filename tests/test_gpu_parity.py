@@ -224,10 +224,12 @@ def _water64_oracle_build():
     return g, D
 
 
-def _water64_bench_context(cache_name="water64_mi355x.json"):
+def _water64_bench_context(cache_name="water64_mi355x.json", tau_prim=0.0):
     from paper_2510_24968_amd import autotune
     b, w = synth.workload("water64")
     ctx = _ctx(b, tau=w["tau"], tau_fp32=w["tau_fp32"])
+    if tau_prim:
+        ctx.set_prim_screen(tau_prim)
     _, st = ctx.schwarz_screen()
     root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
     cache = os.path.join(root, "paper_2510_24968_amd", "tuning", cache_name)
@@ -235,17 +237,19 @@ def _water64_bench_context(cache_name="water64_mi355x.json"):
     return ctx, st, b, w
 
 
-def test_water64_bench_configuration_against_oracle_build():
+@pytest.mark.parametrize("tau_prim", [0.0, 1e-15])
+def test_water64_bench_configuration_against_oracle_build(tau_prim):
     """The 64-water workload in the launch configuration the benchmark times
     (committed tuning cache, per-XCD accumulators, FP32 tiles below 1e-5 in
-    the mixed build), at the oracle's core-Hamiltonian density of the whole
+    the mixed build; every primitive pair, and with primitive-pair screening
+    at 1e-4 tau), at the oracle's core-Hamiltonian density of the whole
     cluster, against one stored oracle Fock build at that density: the
     electronic energy, Tr(DJ), Tr(DK) and 3,144 J and K elements (every
     diagonal element, pairs inside molecules, between nearest neighbours and
     uniformly random ones).  The screened quartet count must equal the
     oracle's, and J, K stay exactly symmetric."""
     g, D = _water64_oracle_build()
-    ctx, st, b, w = _water64_bench_context()
+    ctx, st, b, w = _water64_bench_context(tau_prim=tau_prim)
     assert st["quartets_kept"] == g["screened_quartets"]
     assert st["quartets_total"] == g["canonical_quartets"]
     el = g["elements"]

@@ -287,8 +287,13 @@ fsim_status fsim_get_class_profile(fsim_ctx *ctx, fsim_class_profile *out, int32
  * run variant 2), variant 6 the one-wave-per-quartet kernel whose two
  * Hermite contraction steps run as dense products on the matrix cores
  * (16x16x4 FP64 / FP32 MFMA; classes with a d bra pair, others run variant
- * 3).  waves_per_block is 1, 2 or 4 (variants 3, 5 and 6 use one block
- * shape). */
+ * 3).  waves_per_block is 1, 2 or 4 for launches over tiles, every K'
+ * term a global atomic (variants 3 and 6 use one block shape), or 8 for the
+ * segment mode of the lane variants 0, 1, 2, 4 and 5 (see
+ * fsim_set_krow_lds: blocks of 8 waves, or 4 for kernels held to one wave
+ * per SIMD, over segments of one bra's tiles with the bra's K' rows in LDS;
+ * launches whose rows do not fit run over tiles with 4 waves per block).
+ * The default is variant 1 in segment mode. */
 typedef struct {
     int32_t bra_class, ket_class;   /* pair classes, bra >= ket */
     int32_t fp32;
@@ -371,6 +376,20 @@ fsim_status fsim_set_graph(fsim_ctx *ctx, int32_t enable);
  * launch is captured in graphs like the others.  enable = 0 (default):
  * per-class launches with the tuned variants.  Drops captured graphs. */
 fsim_status fsim_set_persistent(fsim_ctx *ctx, int32_t enable);
+
+/* enable != 0 (default): lane-kernel launches tuned to segment mode
+ * (waves_per_block = 8) take whole
+ * segments of up to 64 tiles of one bra pair per workgroup and add the
+ * quartets' K' terms, which all lie in the rows of the bra's functions
+ * (Eq. fock: K'_ac, K'_ad, K'_bc, K'_bd), into an LDS copy of those rows;
+ * the non-zero entries go to global K' once per segment.  A launch whose
+ * rows (ncart(l_a) + ncart(l_b) rows of N doubles, N the largest molecule)
+ * do not fit in LDS next to the kernel's own use, and incremental (ΔD)
+ * builds, add every K' term with a global atomic instead, as enable = 0
+ * does everywhere (segment-mode settings then run over tiles with 4 waves
+ * per block).  Results differ only in summation order.  Drops captured
+ * graphs. */
+fsim_status fsim_set_krow_lds(fsim_ctx *ctx, int32_t enable);
 
 /* Primitive-pair screening (an addition to the shell-quartet screen of
  * Sec. 5, which keeps every primitive of a kept shell pair).  For primitive

@@ -127,6 +127,9 @@ struct fsim_ctx {
     // counters: one per part)
     bool persistent = false;
     int *pcounter = nullptr;
+    // lane-kernel launches accumulate each bra's K' rows in LDS over
+    // segments of its tiles (default), or add every K' term globally
+    bool krow_lds = true;
     // captured Fock build (hipGraph), one per precision
     bool graph_enabled = false;
     hipStream_t gstream = nullptr;
@@ -482,7 +485,7 @@ static fsim_status create_impl(const fsim_basis *mols, int nmol, const fsim_opti
         for (int Y = 0; Y < NPCLASS; ++Y)
             for (int f = 0; f < 2; ++f) {
                 c->variant[X][Y][f] = ERI_DEFAULT_VARIANT;
-                c->wpb[X][Y][f] = 4;
+                c->wpb[X][Y][f] = 8;
                 c->tuned_ms[X][Y][f] = 0.0;
             }
     c->nmol = nmol;
@@ -984,6 +987,21 @@ static fsim_status upload_list(DevPool &pool, TileList &tl, const std::vector<in
     HIPCHK(hipMemcpy(tl.bra, bra.data(), sizeof(int) * bra.size(), hipMemcpyHostToDevice));
     HIPCHK(hipMemcpy(tl.ket_lo, lo.data(), sizeof(int) * bra.size(), hipMemcpyHostToDevice));
     HIPCHK(hipMemcpy(tl.ket_hi, hi.data(), sizeof(int) * bra.size(), hipMemcpyHostToDevice));
+    // segments of at most SEG_TILES tiles, each within one bra record
+    std::vector<int> srec, st0, snt;
+    for (size_t i = 0; i < bra.size(); ++i)
+        for (int t = start[i]; t < start[i + 1]; t += SEG_TILES) {
+            srec.push_back((int)i);
+            st0.push_back(t);
+            snt.push_back(std::min(SEG_TILES, start[i + 1] - t));
+        }
+    tl.nseg = (int)srec.size();
+    HIPCHK(pool.alloc(&tl.seg_rec, srec.size()));
+    HIPCHK(pool.alloc(&tl.seg_t0, st0.size()));
+    HIPCHK(pool.alloc(&tl.seg_nt, snt.size()));
+    HIPCHK(hipMemcpy(tl.seg_rec, srec.data(), sizeof(int) * srec.size(), hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(tl.seg_t0, st0.data(), sizeof(int) * st0.size(), hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(tl.seg_nt, snt.data(), sizeof(int) * snt.size(), hipMemcpyHostToDevice));
     return FSIM_OK;
 }
 
@@ -1166,6 +1184,9 @@ extern "C" fsim_status fsim_schwarz_screen(fsim_ctx *c, double tau, double tau32
                 d = *full[k];
                 d.ntile = 0;
                 d.nquartet = 0;
+                // density-screened ket ends change the tiles: no segments
+                d.nseg = 0;
+                d.seg_rec = d.seg_t0 = d.seg_nt = nullptr;
                 cl.dnq[k] = 0;
                 cl.dstart[k].assign(d.nbra + 1, 0);
                 cl.dhi[k] = cl.host[k].lo;
@@ -1291,6 +1312,7 @@ static fsim_status enqueue_build(fsim_ctx *c, const double *D, double *F, double
     }
     PersistArgs pa[2];
     bool have_pa[2] = {false, false};
+    const int maxn = *std::max_element(c->mol_n.begin(), c->mol_n.end());
     if (persist) HIPCHK(fill_int(c->pcounter, 2, 0, s));
     // heaviest classes (highest L) first
     for (int X = NPCLASS - 1; X >= 0; --X)
@@ -1356,6 +1378,7 @@ static fsim_status enqueue_build(fsim_ctx *c, const double *D, double *F, double
                 a.mol_off = c->d_mol_off;
                 a.mol_n = c->d_mol_n;
                 a.boys = c->boys;
+                a.kn = c->krow_lds && tl.nseg > 0 ? maxn : 0;
                 const int f32 = mixed && part == 1;
                 if (c->stored && !dref) {
                     a.out = c->store + c->store_off[X][Y];
@@ -1832,8 +1855,9 @@ extern "C" fsim_status fsim_set_tuning(fsim_ctx *c, const fsim_tuning *t, int32_
             return fail(FSIM_EINVAL, "tuning record names no quartet class");
         if (r.variant < 0 || r.variant >= ERI_NVARIANT)
             return fail(FSIM_EINVAL, "variant must be 0.." + std::to_string(ERI_NVARIANT - 1));
-        if (r.waves_per_block != 1 && r.waves_per_block != 2 && r.waves_per_block != 4)
-            return fail(FSIM_EINVAL, "waves_per_block must be 1, 2 or 4");
+        if (r.waves_per_block != 1 && r.waves_per_block != 2 && r.waves_per_block != 4 &&
+            r.waves_per_block != 8)
+            return fail(FSIM_EINVAL, "waves_per_block must be 1, 2, 4 or 8");
     }
     for (int32_t k = 0; k < n; ++k) {
         const fsim_tuning &r = t[k];
@@ -1841,6 +1865,13 @@ extern "C" fsim_status fsim_set_tuning(fsim_ctx *c, const fsim_tuning *t, int32_
         c->wpb[r.bra_class][r.ket_class][r.fp32] = r.waves_per_block;
         c->tuned_ms[r.bra_class][r.ket_class][r.fp32] = r.ms;
     }
+    drop_graphs(c);
+    return FSIM_OK;
+}
+
+extern "C" fsim_status fsim_set_krow_lds(fsim_ctx *c, int32_t enable) {
+    if (!c) return fail(FSIM_EINVAL, "ctx is NULL");
+    c->krow_lds = enable != 0;
     drop_graphs(c);
     return FSIM_OK;
 }
@@ -1913,7 +1944,8 @@ extern "C" fsim_status fsim_autotune(fsim_ctx *c, const double *D, fsim_precisio
                 bv[X][Y][f] = c->variant[X][Y][f];
                 bw[X][Y][f] = c->wpb[X][Y][f];
             }
-    const int wpbs[3] = {1, 2, 4};
+    // 8: segment mode (K' rows in LDS) for the lane kernels
+    const int wpbs[4] = {1, 2, 4, 8};
     fsim_status st = FSIM_OK;
     // FSIM_AUTOTUNE_VERBOSE=1: one progress line per timed pass on stderr
     const char *vb = std::getenv("FSIM_AUTOTUNE_VERBOSE");
@@ -1921,9 +1953,12 @@ extern "C" fsim_status fsim_autotune(fsim_ctx *c, const double *D, fsim_precisio
     // one warm-up build
     st = fock_build(c, D, c->F, nullptr, nullptr, nullptr, prec, s);
     for (int v = 0; v < ERI_NVARIANT && st == FSIM_OK; ++v)
-        for (int w = 0; w < 3 && st == FSIM_OK; ++w) {
-            if ((v == ERI_VARIANT_WAVE || v == ERI_VARIANT_WIDE || v == ERI_VARIANT_MFMA) && w > 0)
+        for (int w = 0; w < 4 && st == FSIM_OK; ++w) {
+            if ((v == ERI_VARIANT_WAVE || v == ERI_VARIANT_MFMA) && w > 0)
                 continue;   // one block shape
+            if (v == ERI_VARIANT_WIDE && w != 0 && w != 3)
+                continue;   // one wave per block, or segment mode
+            if (w == 3 && !c->krow_lds) continue;
             // the wave kernel is only a candidate for the high angular-momentum
             // classes (L >= 5) and the ket-outer kernel only for the ss, ps, pp
             // and ds bras;

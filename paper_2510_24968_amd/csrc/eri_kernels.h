@@ -158,12 +158,18 @@ __host__ __device__ constexpr int n_chunks(int la, int lb, int lc, int ld, int l
 // J'_ab += 2 v D_cd (wave-reduced), J'_cd += 2 v D_ab, K'_ac += v D_bd,
 // K'_bc += v D_ad, K'_ad += v D_bc, K'_bd += v D_ac (fac: degeneracy factor,
 // 0 for an idle lane).
+//
+// With kl, the K' terms go to the block's LDS rows instead (krow: row x < NA
+// is K'_{f1 + x, .}, row NA + y is K'_{f2 + y, .}, kn doubles per row),
+// which the kernel flushes to global memory once per segment of tiles.
 template <int LA, int LB, int LC, int LD, typename T, int A0, int A1, int CD0, int CD1>
 __device__ __forceinline__ void digest_chunk(const T (&out)[(A1 - A0) * ncart(LB)][CD1 - CD0],
                                              const double *__restrict__ D, double *__restrict__ Jh,
                                              double *__restrict__ Kh, int N, int f1, int f2, int f3,
-                                             int f4, double fac, bool active) {
-    constexpr int NB = ncart(LB), NC = ncart(LC), ND = ncart(LD);
+                                             int f4, double fac, bool active,
+                                             double *__restrict__ krow = nullptr, int kn = 0,
+                                             bool kl = false) {
+    constexpr int NA = ncart(LA), NB = ncart(LB), NC = ncart(LC), ND = ncart(LD);
     constexpr int NAc = A1 - A0, NABc = NAc * NB, NCDc = CD1 - CD0;
     const int lane = threadIdx.x & 63;
     // J'_ab (partial over this chunk's cd): pre-reduced over the wave
@@ -210,7 +216,8 @@ __device__ __forceinline__ void digest_chunk(const T (&out)[(A1 - A0) * ncart(LB
                                        D[(size_t)(f2 + ib) * N + f4 + id];
                         });
                     });
-                    atomicAdd(&Kh[(size_t)(f1 + A0 + al) * N + f3 + ic], fac * sum);
+                    if (kl) atomicAdd(&krow[(A0 + al) * kn + f3 + ic], fac * sum);
+                    else atomicAdd(&Kh[(size_t)(f1 + A0 + al) * N + f3 + ic], fac * sum);
                 });
                 static_for<NB>([&](auto b_) {
                     constexpr int ib = decltype(b_)::value;
@@ -225,7 +232,8 @@ __device__ __forceinline__ void digest_chunk(const T (&out)[(A1 - A0) * ncart(LB
                                        D[(size_t)(f1 + A0 + al) * N + f4 + id];
                         });
                     });
-                    atomicAdd(&Kh[(size_t)(f2 + ib) * N + f3 + ic], fac * sum);
+                    if (kl) atomicAdd(&krow[(NA + ib) * kn + f3 + ic], fac * sum);
+                    else atomicAdd(&Kh[(size_t)(f2 + ib) * N + f3 + ic], fac * sum);
                 });
             }
         });
@@ -251,7 +259,8 @@ __device__ __forceinline__ void digest_chunk(const T (&out)[(A1 - A0) * ncart(LB
                                        D[(size_t)(f2 + ib) * N + f3 + ic];
                         });
                     });
-                    atomicAdd(&Kh[(size_t)(f1 + A0 + al) * N + f4 + id], fac * sum);
+                    if (kl) atomicAdd(&krow[(A0 + al) * kn + f4 + id], fac * sum);
+                    else atomicAdd(&Kh[(size_t)(f1 + A0 + al) * N + f4 + id], fac * sum);
                 });
                 static_for<NB>([&](auto b_) {
                     constexpr int ib = decltype(b_)::value;
@@ -266,10 +275,47 @@ __device__ __forceinline__ void digest_chunk(const T (&out)[(A1 - A0) * ncart(LB
                                        D[(size_t)(f1 + A0 + al) * N + f3 + ic];
                         });
                     });
-                    atomicAdd(&Kh[(size_t)(f2 + ib) * N + f4 + id], fac * sum);
+                    if (kl) atomicAdd(&krow[(NA + ib) * kn + f4 + id], fac * sum);
+                    else atomicAdd(&Kh[(size_t)(f2 + ib) * N + f4 + id], fac * sum);
                 });
             }
         });
+    }
+}
+
+// Segment mode of the lane kernels (Fock builds): the block takes whole
+// segments, each a run of tiles of one bra record, and its waves split the
+// segment's tiles.  The K' terms of a quartet all lie in the rows of the
+// bra's functions (K'_ac, K'_ad in the rows of a, K'_bc, K'_bd in those of
+// b), so they are added into the block's LDS copy of those rows; after a
+// block barrier the non-zero entries go to global K' with one atomic each
+// and the rows are cleared.  krow: (NA + NB) rows of a.kn doubles.
+template <int NA, int NB, typename Body>
+__device__ __forceinline__ void run_segments(const EriArgs &a, double *__restrict__ krow,
+                                             long long xoff, Body &&body) {
+    constexpr int NR = NA + NB;
+    const int wave = threadIdx.x >> 6, wpb = blockDim.x >> 6;
+    const int kn = a.kn;
+    for (int x = threadIdx.x; x < NR * kn; x += blockDim.x) krow[x] = 0.0;
+    __syncthreads();
+    for (int sg = blockIdx.x; sg < a.tl.nseg; sg += gridDim.x) {
+        const int t0 = a.tl.seg_t0[sg], nt = a.tl.seg_nt[sg];
+        for (int t = t0 + wave; t < t0 + nt; t += wpb) body(__builtin_amdgcn_readfirstlane(t));
+        __syncthreads();
+        const int bra = a.tl.bra[a.tl.seg_rec[sg]];
+        const int mol = a.bra.mol[bra];
+        const int N = a.mol_n[mol];
+        const int f1 = a.bra.bf1[bra], f2 = a.bra.bf2[bra];
+        double *__restrict__ Kh = a.Kh + xoff + a.mol_off[mol];
+        for (int x = threadIdx.x; x < NR * N; x += blockDim.x) {
+            const int r = x / N, col = x - r * N;
+            const double v = krow[r * kn + col];
+            if (v != 0.0) {
+                atomicAdd(&Kh[(size_t)(r < NA ? f1 + r : f2 + r - NA) * N + col], v);
+                krow[r * kn + col] = 0.0;
+            }
+        }
+        __syncthreads();
     }
 }
 
@@ -281,8 +327,15 @@ __host__ __device__ constexpr int lane_min_waves(int la, int lb, int lc, int ld,
     return la == 2 && lane_live(la, lb, lc, ld, ca, cdc) <= 128 ? 2 : 1;
 }
 
-template <int LA, int LB, int LC, int LD, typename T, bool STORE, int CA, int CDC>
-__global__ __launch_bounds__(256, lane_min_waves(LA, LB, LC, LD, CA, CDC)) void k_eri_lane(EriArgs a) {
+// Blocks of the lane kernel in segment mode: 8 waves where the kernel is held
+// to two waves per SIMD (two blocks' worth of registers per CU), else 4.
+__host__ __device__ constexpr int seg_waves(int la, int lb, int lc, int ld, int ca, int cdc) {
+    return lane_min_waves(la, lb, lc, ld, ca, cdc) == 2 ? 8 : 4;
+}
+
+template <int LA, int LB, int LC, int LD, typename T, bool STORE, int CA, int CDC, bool SEG>
+__global__ __launch_bounds__(SEG ? 64 * seg_waves(LA, LB, LC, LD, CA, CDC) : 256,
+                             lane_min_waves(LA, LB, LC, LD, CA, CDC)) void k_eri_lane(EriArgs a) {
     constexpr int L = LA + LB + LC + LD, LAB = LA + LB;
     constexpr int NA = ncart(LA), NB = ncart(LB), NC = ncart(LC), ND = ncart(LD);
     constexpr int NCD = NC * ND, NHAB = nherm(LAB), NH = nherm(L);
@@ -327,9 +380,9 @@ __global__ __launch_bounds__(256, lane_min_waves(LA, LB, LC, LD, CA, CDC)) void 
     // per-XCD private J'/K' copies keep each cache line's atomics on one XCD
     const long long xoff = (!STORE && a.xcd_stride) ? xcd_index() * a.xcd_stride : 0;
 
-    for (int tile0 = blockIdx.x * wpb + (threadIdx.x >> 6); tile0 < ntile;
-         tile0 += gridDim.x * wpb) {
-        const int tile = __builtin_amdgcn_readfirstlane(tile0);
+    // one tile; kl: K' rows into the block's LDS rows krow (segment mode)
+    auto tile_body = [&](const int tile, double *__restrict__ krow,
+                         const bool kl) __attribute__((always_inline)) {
         int bra, ket;
         bool active;
         if constexpr (STORE) {
@@ -534,9 +587,19 @@ __global__ __launch_bounds__(256, lane_min_waves(LA, LB, LC, LD, CA, CDC)) void 
                 }
             } else {
                 digest_chunk<LA, LB, LC, LD, T, A0, A1, CD0, CD1>(out, D, Jh, Kh, N, f1, f2, f3, f4,
-                                                                  fac, active);
+                                                                  fac, active, krow, a.kn, kl);
             }
         });
+    };
+    if constexpr (SEG && !STORE) {
+        double *__restrict__ krow = (double *)(stage_lds + (size_t)wpb * a.stage_bytes);
+        run_segments<NA, NB>(a, krow, xoff, [&](int t) __attribute__((always_inline)) {
+            tile_body(t, krow, true);
+        });
+    } else {
+        for (int tile0 = blockIdx.x * wpb + (threadIdx.x >> 6); tile0 < ntile;
+             tile0 += gridDim.x * wpb)
+            tile_body(__builtin_amdgcn_readfirstlane(tile0), nullptr, false);
     }
 }
 
@@ -573,7 +636,8 @@ struct BoysStagedMixed {
 // a.stage_prims of them).
 template <int LA, int LB, int LC, int LD, typename T, bool STORE, int CA, int CDC, typename BP>
 __device__ __forceinline__ void ko_tile(const EriArgs &a, const int tile, const BP &bp,
-                                        double *__restrict__ sp) {
+                                        double *__restrict__ sp, double *__restrict__ krow = nullptr,
+                                        bool kl = false) {
     constexpr int L = LA + LB + LC + LD, LAB = LA + LB;
     constexpr int NA = ncart(LA), NB = ncart(LB), NC = ncart(LC), ND = ncart(LD);
     constexpr int NCD = NC * ND, NHAB = nherm(LAB), NH = nherm(L);
@@ -766,13 +830,13 @@ __device__ __forceinline__ void ko_tile(const EriArgs &a, const int tile, const 
             }
         } else {
             digest_chunk<LA, LB, LC, LD, T, A0, A1, CD0, CD1>(out, D, Jh, Kh, N, f1, f2, f3,
-                                                              f4, fac, active);
+                                                              f4, fac, active, krow, a.kn, kl);
         }
     });
 }
 
-template <int LA, int LB, int LC, int LD, typename T, bool STORE, int CA, int CDC>
-__global__ __launch_bounds__(256) void k_eri_lane_ko(EriArgs a) {
+template <int LA, int LB, int LC, int LD, typename T, bool STORE, int CA, int CDC, bool SEG>
+__global__ __launch_bounds__(SEG ? 512 : 256) void k_eri_lane_ko(EriArgs a) {
     constexpr int L = LA + LB + LC + LD;
     // Boys grid in LDS: FP64 for FP64 tiles, FP32 (5 terms, the Taylor step
     // only) for FP32 tiles
@@ -788,10 +852,19 @@ __global__ __launch_bounds__(256) void k_eri_lane_ko(EriArgs a) {
     double *__restrict__ sp = (double *)(stage_lds + (size_t)(threadIdx.x >> 6) * a.stage_bytes);
     using BP = std::conditional_t<F32, BoysStagedMixed, BoysStaged64>;
     const BP bp{tab};
-    for (int tile0 = blockIdx.x * wpb + (threadIdx.x >> 6); tile0 < ntile;
-         tile0 += gridDim.x * wpb)
-        ko_tile<LA, LB, LC, LD, T, STORE, CA, CDC>(a, __builtin_amdgcn_readfirstlane(tile0), bp,
-                                                   sp);
+    if constexpr (SEG && !STORE) {
+        // segment mode: blocks of 8 waves share the bra's K' rows
+        double *__restrict__ krow = (double *)(stage_lds + (size_t)wpb * a.stage_bytes);
+        const long long xoff = a.xcd_stride ? xcd_index() * a.xcd_stride : 0;
+        run_segments<ncart(LA), ncart(LB)>(a, krow, xoff, [&](int t) __attribute__((always_inline)) {
+            ko_tile<LA, LB, LC, LD, T, STORE, CA, CDC>(a, t, bp, sp, krow, true);
+        });
+    } else {
+        for (int tile0 = blockIdx.x * wpb + (threadIdx.x >> 6); tile0 < ntile;
+             tile0 += gridDim.x * wpb)
+            ko_tile<LA, LB, LC, LD, T, STORE, CA, CDC>(a, __builtin_amdgcn_readfirstlane(tile0),
+                                                       bp, sp);
+    }
 }
 
 // ===========================================================================
@@ -1488,6 +1561,29 @@ void launch_mfma_kernel(int ntile, const EriArgs &a, hipStream_t s) {
     hipLaunchKernelGGL((k_eri_mfma<LA, LB, LC, LD, T, STORE>), dim3(blocks), dim3(64), 0, s, a);
 }
 
+// LDS of one workgroup on gfx950.
+constexpr size_t LDS_PER_CU = 160 * 1024;
+
+// Segment mode of a lane-kernel launch (waves_per_block = 8 in a Fock build
+// with a.kn > 0 and a segment list): W-wave blocks over segments, the
+// dynamic LDS holding the W staging slices and the bra's K' rows.  False
+// (the caller then launches the tile-mode kernel with kn = 0) when the rows
+// do not fit next to the kernel's static LDS.
+template <int LA, int LB>
+bool segment_fit(const void *kernel, int W, EriArgs &b, int &blocks, size_t &dyn) {
+    if (b.kn <= 0 || b.tl.nseg <= 0) return false;
+    const size_t rows = (size_t)(ncart(LA) + ncart(LB)) * b.kn * sizeof(double);
+    hipFuncAttributes fa{};
+    if (hipFuncGetAttributes(&fa, kernel) != hipSuccess) {
+        (void)hipGetLastError();
+        return false;
+    }
+    dyn = (size_t)W * b.stage_bytes + rows;
+    if (fa.sharedSizeBytes + dyn > LDS_PER_CU) return false;
+    blocks = b.tl.nseg < 8192 ? b.tl.nseg : 8192;
+    return true;
+}
+
 template <int LA, int LB, int LC, int LD, typename T, bool STORE, int BUDGET>
 void launch_budget(int ntile, int wpb, const EriArgs &a, hipStream_t s) {
     if constexpr (lane_fits<LA, LB, LC, LD, BUDGET>()) {
@@ -1500,8 +1596,24 @@ void launch_budget(int ntile, int wpb, const EriArgs &a, hipStream_t s) {
         b.stage_prims = STAGE_BYTES / per_prim < 1 ? 1 : STAGE_BYTES / per_prim;
         if (b.stage_prims > a.bra.kmax) b.stage_prims = a.bra.kmax > 0 ? a.bra.kmax : 1;
         b.stage_bytes = LA == 2 ? (b.stage_prims * per_prim + 15) / 16 * 16 : 0;
-        hipLaunchKernelGGL((k_eri_lane<LA, LB, LC, LD, T, STORE, CA, CDC>), dim3(blocks),
-                           dim3(64 * wpb), (size_t)wpb * b.stage_bytes, s, b);
+        if constexpr (!STORE) {
+            if (wpb == 8) {
+                constexpr int W = seg_waves(LA, LB, LC, LD, CA, CDC);
+                auto seg = k_eri_lane<LA, LB, LC, LD, T, false, CA, CDC, true>;
+                int sblocks = 0;
+                size_t dyn = 0;
+                if (segment_fit<LA, LB>((const void *)seg, W, b, sblocks, dyn)) {
+                    hipLaunchKernelGGL(seg, dim3(sblocks), dim3(64 * W), dyn, s, b);
+                    return;
+                }
+            }
+        }
+        b.kn = 0;
+        const int w = wpb > 4 ? 4 : wpb;
+        blocks = (ntile + w - 1) / w;
+        if (blocks > 8192) blocks = 8192;
+        hipLaunchKernelGGL((k_eri_lane<LA, LB, LC, LD, T, STORE, CA, CDC, false>), dim3(blocks),
+                           dim3(64 * w), (size_t)w * b.stage_bytes, s, b);
     } else {
         launch_wave_kernel<LA, LB, LC, LD, T, STORE>(ntile, a, s);
     }
@@ -1518,10 +1630,23 @@ void launch_ko(int ntile, int wpb, const EriArgs &a, hipStream_t s) {
             EriArgs b = a;
             b.stage_prims = kmax;
             b.stage_bytes = (kmax * per_prim + 15) / 16 * 16;
-            int blocks = (ntile + wpb - 1) / wpb;
+            if constexpr (!STORE) {
+                if (wpb == 8) {
+                    auto seg = k_eri_lane_ko<LA, LB, LC, LD, T, false, CA, CDC, true>;
+                    int sblocks = 0;
+                    size_t dyn = 0;
+                    if (segment_fit<LA, LB>((const void *)seg, 8, b, sblocks, dyn)) {
+                        hipLaunchKernelGGL(seg, dim3(sblocks), dim3(512), dyn, s, b);
+                        return;
+                    }
+                }
+            }
+            b.kn = 0;
+            const int w = wpb > 4 ? 4 : wpb;
+            int blocks = (ntile + w - 1) / w;
             if (blocks > 8192) blocks = 8192;
-            hipLaunchKernelGGL((k_eri_lane_ko<LA, LB, LC, LD, T, STORE, CA, CDC>), dim3(blocks),
-                               dim3(64 * wpb), (size_t)wpb * b.stage_bytes, s, b);
+            hipLaunchKernelGGL((k_eri_lane_ko<LA, LB, LC, LD, T, STORE, CA, CDC, false>),
+                               dim3(blocks), dim3(64 * w), (size_t)w * b.stage_bytes, s, b);
             return;
         }
     }
@@ -1559,7 +1684,7 @@ template <int LA, int LB, int LC, int LD, typename T>
 hipError_t launch_class(bool store, int variant, int wpb, const EriArgs &a, hipStream_t s) {
     const int ntile = store ? a.st_ntile : a.tl.ntile;
     if (ntile <= 0) return hipSuccess;
-    if (wpb < 1 || wpb > 4) wpb = 4;
+    if (wpb != 1 && wpb != 2 && wpb != 4 && wpb != 8) wpb = 4;
     if (store) launch_variant<LA, LB, LC, LD, T, true>(ntile, variant, wpb, a, s);
     else launch_variant<LA, LB, LC, LD, T, false>(ntile, variant, wpb, a, s);
     return hipGetLastError();

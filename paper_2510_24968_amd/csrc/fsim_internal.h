@@ -137,9 +137,15 @@ struct TileList {
     int *bra = nullptr;          // [nbra]
     int *ket_lo = nullptr;       // [nbra]
     int *ket_hi = nullptr;       // [nbra]
+    // segments (Fock builds with K' rows in LDS): segment s is the tiles
+    // [seg_t0[s], seg_t0[s] + seg_nt[s]) of bra record seg_rec[s], at most
+    // SEG_TILES of them; nseg = 0: no segments
+    int nseg = 0;
+    int *seg_rec = nullptr, *seg_t0 = nullptr, *seg_nt = nullptr;
 };
 
-constexpr int TILE = 64;   // kets per wave tile (one per lane)
+constexpr int TILE = 64;        // kets per wave tile (one per lane)
+constexpr int SEG_TILES = 64;   // tiles per segment
 
 struct EriArgs {
     PairTable bra, ket;
@@ -168,6 +174,11 @@ struct EriArgs {
     const int *st_stride;   // [4 per task]
     double *out;
     const double *boys;     // [BOYS_NT][BOYS_NORD]
+    // > 0: segment mode of the lane kernels, the K' rows of each segment's
+    // bra accumulate in LDS, kn doubles per row (the largest N_m); the
+    // dynamic LDS holds (ncart(la) + ncart(lb)) * kn doubles after the
+    // waves' staging slices.  0: every K' term is a global atomic.
+    int kn;
 };
 
 

@@ -119,6 +119,7 @@ def lib():
         "fsim_set_xcd_private": [vp, i32],
         "fsim_set_persistent": [vp, i32],
         "fsim_set_prim_screen": [vp, dbl],
+        "fsim_set_krow_lds": [vp, i32],
         "fsim_set_tuning": [vp, vp, i32],
         "fsim_get_tuning": [vp, vp, i32, ctypes.POINTER(i32)],
         "fsim_autotune": [vp, vp, ctypes.c_int, vp],
@@ -292,6 +293,16 @@ class Context:
         """Per-XCD private J'/K' accumulators (default on) or one shared copy."""
         _check(lib().fsim_set_xcd_private(self.h, 1 if enable else 0))
 
+    def set_graph(self, enable=True):
+        """Replay Fock builds that ask for F only from a captured hipGraph
+        (fsim_set_graph)."""
+        _check(lib().fsim_set_graph(self.h, 1 if enable else 0))
+
+    def set_krow_lds(self, enable=True):
+        """K' rows of each bra accumulated in LDS over segments of its tiles
+        (default) or every K' term added globally (fsim_set_krow_lds)."""
+        _check(lib().fsim_set_krow_lds(self.h, 1 if enable else 0))
+
     def set_prim_screen(self, tau_prim):
         """Primitive-pair screening at tau_prim (0: off) for the next
         schwarz_screen (fsim_set_prim_screen); the current screen is
@@ -464,8 +475,6 @@ class Batch(Context):
         _check(lib().fsim_batch_scf_info(self.h, arr))
         return [_struct_dict(arr[k]) for k in range(self.nmol)]
 
-    def set_graph(self, enable=True):
-        _check(lib().fsim_set_graph(self.h, 1 if enable else 0))
 
     def one_electron(self):
         S, H, X = self._mat(), self._mat(), self._mat()

@@ -502,12 +502,16 @@ def test_every_kernel_variant_matches_oracle(variant):
     D = _random_density(ctx.nbf, 5)
     Jo, Ko = oracle.Basis(b).fock_jk(D, tau=0.0)
     sJ, sK = np.max(np.abs(Jo)), np.max(np.abs(Ko))
-    for wpb in (1, 2, 4):
+    for wpb, krow in ((1, True), (2, True), (4, True), (8, True), (8, False)):
+        # over tiles with 1, 2, 4 waves per block; segment mode (K' rows in
+        # LDS); segment-mode settings with the rows switched off
+        ctx.set_krow_lds(krow)
+        ctx32.set_krow_lds(krow)
         ctx.set_all_variants(variant, wpb)
         ctx32.set_all_variants(variant, wpb)
         r = ctx.fock_build(_dev(D), precision="fp64", want_jk=True)
-        assert np.max(np.abs(r["J"].cpu().numpy() - Jo)) < 1e-11, (variant, wpb)
-        assert np.max(np.abs(r["K"].cpu().numpy() - Ko)) < 1e-11, (variant, wpb)
+        assert np.max(np.abs(r["J"].cpu().numpy() - Jo)) < 1e-11, (variant, wpb, krow)
+        assert np.max(np.abs(r["K"].cpu().numpy() - Ko)) < 1e-11, (variant, wpb, krow)
         r = ctx32.fock_build(_dev(D), precision="mixed", want_jk=True)
         dJ = np.max(np.abs(r["J"].cpu().numpy() - Jo))
         dK = np.max(np.abs(r["K"].cpu().numpy() - Ko))
@@ -517,7 +521,46 @@ def test_every_kernel_variant_matches_oracle(variant):
         assert dJ > 0                                        # the FP32 kernels did run
 
 
-@pytest.mark.parametrize("wpb", [1, 4])
+def test_krow_lds_segments_water16():
+    """Sixteen waters (336 functions; bras own up to thousands of kets, so
+    a bra's tiles span several segments): the FP64 and mixed builds with
+    K' rows accumulated in LDS per segment equal the builds with every K'
+    term a global atomic up to summation order, and the FP64 one matches
+    the oracle's J and K at sampled elements; also under graph replay."""
+    b = synth.water_cluster(16, 4)
+    ctx = _ctx(b, tau=1e-11, tau_fp32=1e-6)
+    ctx.set_prim_screen(1e-15)
+    ctx.schwarz_screen()
+    D = _dev(_random_density(ctx.nbf, 31) * 0.05)
+    res = {}
+    for variant in (4, 1):       # ket-outer and bra-outer lane kernels
+        ctx.set_all_variants(variant, 8)
+        for krow in (False, True):
+            ctx.set_krow_lds(krow)
+            for prec in ("fp64", "mixed"):
+                r = ctx.fock_build(D, precision=prec, want_jk=True)
+                res[krow, prec] = (r["J"].clone(), r["K"].clone())
+        for prec in ("fp64", "mixed"):
+            for k in (0, 1):
+                d = torch.max(torch.abs(res[True, prec][k] - res[False, prec][k])).item()
+                print(f"water16 variant {variant} {prec} {'JK'[k]}: LDS rows vs global atomics "
+                      f"{d:.2e}", flush=True)
+                assert d < 1e-11
+    rng = np.random.default_rng(16)
+    mus, nus = rng.integers(0, ctx.nbf, 40), rng.integers(0, ctx.nbf, 40)
+    Je, Ke = oracle.Basis(b).jk_elements(D.cpu().numpy(), mus, nus, tau=1e-11)
+    J, K = res[True, "fp64"][0].cpu().numpy(), res[True, "fp64"][1].cpu().numpy()
+    assert np.max(np.abs(J[mus, nus] - Je)) < 1e-10
+    assert np.max(np.abs(K[mus, nus] - Ke)) < 1e-10
+    ctx.set_graph(True)
+    F0 = ctx.fock_build(D, energy=False)["F"].clone()
+    for _ in range(3):
+        F = ctx.fock_build(D, energy=False)["F"]
+        torch.cuda.synchronize()
+        assert torch.max(torch.abs(F - F0)).item() < 1e-11
+
+
+@pytest.mark.parametrize("wpb", [1, 4, 8])
 def test_ket_outer_kernel_water_mixed(wpb):
     """The ket-outer lane kernel on three-primitive s/p shells, in FP64 and
     with FP32 tiles (the weak quartets below 1e-6), against the oracle.  The
@@ -549,7 +592,7 @@ def test_autotune_then_parity():
     D0 = ctx.core_guess()
     table = autotune.tune(ctx, D0)
     assert len(table) > 0
-    assert all(0 <= r["variant"] < 7 and r["waves_per_block"] in (1, 2, 4) for r in table.values())
+    assert all(0 <= r["variant"] < 7 and r["waves_per_block"] in (1, 2, 4, 8) for r in table.values())
     D = D0.cpu().numpy()
     Jo, Ko = oracle.Basis(b).fock_jk(D, tau=tau)
     r = ctx.fock_build(D0, want_jk=True)

@@ -382,11 +382,11 @@ fsim_status fsim_set_persistent(fsim_ctx *ctx, int32_t enable);
  * segments of up to 64 tiles of one bra pair per workgroup and add the
  * quartets' K' terms, which all lie in the rows of the bra's functions
  * (Eq. fock: K'_ac, K'_ad, K'_bc, K'_bd), into an LDS copy of those rows;
- * the non-zero entries go to global K' once per segment.  A launch whose
- * rows (ncart(l_a) + ncart(l_b) rows of N doubles, N the largest molecule)
- * do not fit in LDS next to the kernel's own use, and incremental (ΔD)
- * builds, add every K' term with a global atomic instead, as enable = 0
- * does everywhere (segment-mode settings then run over tiles with 4 waves
+ * the non-zero entries go to global K' once per segment (incremental
+ * builds cut their segments again for every build).  A launch whose rows
+ * (ncart(l_a) + ncart(l_b) rows of N doubles, N the largest molecule) do
+ * not fit in LDS next to the kernel's own use adds every K' term with a
+ * global atomic instead, as enable = 0 does everywhere (segment-mode settings then run over tiles with 4 waves
  * per block).  Results differ only in summation order.  Drops captured
  * graphs. */
 fsim_status fsim_set_krow_lds(fsim_ctx *ctx, int32_t enable);

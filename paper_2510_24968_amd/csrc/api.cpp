@@ -69,6 +69,7 @@ struct ClassLists {
     HostList host[3];
     TileList delta[3];
     std::vector<int> dstart[3], dhi[3];
+    std::vector<int> dseg[3];   // segments of the delta lists: rec, t0, nt (3 arrays)
     int64_t dnq[3] = {0, 0, 0};
 };
 
@@ -1184,15 +1185,22 @@ extern "C" fsim_status fsim_schwarz_screen(fsim_ctx *c, double tau, double tau32
                 d = *full[k];
                 d.ntile = 0;
                 d.nquartet = 0;
-                // density-screened ket ends change the tiles: no segments
+                // density-screened ket ends change the tiles: segments are
+                // cut again for every build, at most as many as the full list's
                 d.nseg = 0;
                 d.seg_rec = d.seg_t0 = d.seg_nt = nullptr;
+                cl.dseg[k].assign(3 * (size_t)full[k]->nseg, 0);
                 cl.dnq[k] = 0;
                 cl.dstart[k].assign(d.nbra + 1, 0);
                 cl.dhi[k] = cl.host[k].lo;
                 if (d.nbra == 0) continue;
                 HIPCHK(c->screen_pool.alloc(&d.tile_start, (size_t)d.nbra + 1));
                 HIPCHK(c->screen_pool.alloc(&d.ket_hi, (size_t)d.nbra));
+                if (full[k]->nseg > 0) {
+                    HIPCHK(c->screen_pool.alloc(&d.seg_rec, (size_t)full[k]->nseg));
+                    HIPCHK(c->screen_pool.alloc(&d.seg_t0, (size_t)full[k]->nseg));
+                    HIPCHK(c->screen_pool.alloc(&d.seg_nt, (size_t)full[k]->nseg));
+                }
             }
             S.quartets_kept += cl.all64.nquartet;
             // primitive quartets: sum over kept quartets of K_bra * K_ket
@@ -1738,11 +1746,31 @@ static fsim_status delta_lists(fsim_ctx *c, double thr, hipStream_t s, int64_t *
                 d.ntile = h.bra.empty() ? 0 : st.back();
                 d.nquartet = nq;
                 cl.dnq[li] = nq;
+                // segments over the new tile ranges (never more than the full list's)
+                const size_t cap = cl.dseg[li].size() / 3;
+                int *srec = cl.dseg[li].data(), *st0 = srec + cap, *snt = st0 + cap;
+                size_t ns = 0;
+                for (size_t r = 0; r < h.bra.size() && cap > 0; ++r)
+                    for (int t = st[r]; t < st[r + 1]; t += SEG_TILES) {
+                        srec[ns] = (int)r;
+                        st0[ns] = t;
+                        snt[ns] = std::min(SEG_TILES, st[r + 1] - t);
+                        ++ns;
+                    }
+                d.nseg = (int)ns;
                 if (!h.bra.empty()) {
                     HIPCHK(hipMemcpyAsync(d.tile_start, st.data(), sizeof(int) * st.size(),
                                           hipMemcpyHostToDevice, s));
                     HIPCHK(hipMemcpyAsync(d.ket_hi, hi.data(), sizeof(int) * hi.size(),
                                           hipMemcpyHostToDevice, s));
+                    if (ns > 0) {
+                        HIPCHK(hipMemcpyAsync(d.seg_rec, srec, sizeof(int) * ns,
+                                              hipMemcpyHostToDevice, s));
+                        HIPCHK(hipMemcpyAsync(d.seg_t0, st0, sizeof(int) * ns,
+                                              hipMemcpyHostToDevice, s));
+                        HIPCHK(hipMemcpyAsync(d.seg_nt, snt, sizeof(int) * ns,
+                                              hipMemcpyHostToDevice, s));
+                    }
                 }
                 if (li == 0) total += nq;
             }

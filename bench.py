@@ -50,6 +50,30 @@ def kernel_traffic(workload, dom):
     return None if rec is None else rec["bytes_per_launch"]
 
 
+def kernel_counters(workload, dom):
+    """The dominant kernel's FP64 VALU rate as the SQ instruction counters
+    count it (committed summary of two rocprofv3 counter passes, see
+    paper_2510_24968_amd/prof_sq.py), or None if absent or taken from other
+    kernel sources."""
+    path = os.path.join(ROOT, "profiles", f"k_eri_{workload}_fp64_sq_counters.md")
+    if not os.path.exists(path):
+        return None
+    try:
+        blob = json.loads(open(path).read().split("```json")[1].split("```")[0])
+    except (IndexError, ValueError):
+        return None
+    from paper_2510_24968_amd.prof_traffic import source_digest
+    if blob.get("source_digest") != source_digest():
+        return None
+    rec = blob.get("kernels", {}).get(dom["cls"])
+    if rec is None:
+        return None
+    return {"fp64_tflops_issued": rec["fp64_tflops_issued"],
+            "fp64_frac_of_peak": rec["fp64_frac_of_peak"], "wait": rec["wait"],
+            "valu_busy": rec["valu_busy"], "ms_under_counters": rec["ms_under_counters"],
+            "source": os.path.relpath(path, ROOT)}
+
+
 def stored_oracle_build(workload):
     """The stored oracle Fock build of this workload at the oracle's own
     core-Hamiltonian density (tests/golden/<workload>_fock_oracle.json,
@@ -174,7 +198,12 @@ def run_batch(a, basis_list, w):
     log(f"tuning: {tuning_src or 'library defaults'}")
     tau_prim = 1e-4 * w["tau"] if a.tau_prim is None else a.tau_prim
     all_prims = None
-    if tau_prim > 0:
+    if tau_prim > 0 and a.no_all_prims:
+        bt.set_prim_screen(tau_prim)
+        _, st = bt.schwarz_screen()
+        if tuning_src:
+            autotune.apply(bt, autotune.load(path))
+    elif tau_prim > 0:
         # every primitive pair first: FP64 Fock build at the core guess
         bt.set_persistent(not a.per_class)
         Dg = bt.core_guess()
@@ -337,6 +366,9 @@ def main():
     ap.add_argument("--tuning", default=None,
                     help="autotuner cache (JSON); default: the committed one for this workload")
     ap.add_argument("--autotune", action="store_true", help="tune in-process before timing")
+    ap.add_argument("--no-all-prims", action="store_true",
+                    help="skip the builds with every primitive pair (a trace then holds only "
+                         "the screened builds)")
     ap.add_argument("--tau-prim", type=float, default=None,
                     help="primitive-pair screening threshold (default 1e-4 x the Schwarz tau; "
                          "0: every primitive pair of a kept shell pair)")
@@ -384,9 +416,11 @@ def main():
     all_prims = None
     if tau_prim > 0:
         # every primitive pair first: Fock builds at the core-guess density
-        fb0, E0 = fock_build_times(ctx, a, ctx.core_guess())
+        fb0, E0 = ({"fp64": None}, {}) if a.no_all_prims else \
+            fock_build_times(ctx, a, ctx.core_guess())
         all_prims = {"fock_build_s": fb0,
-                     "quartets_per_s_fp64_build": st["quartets_kept"] / fb0["fp64"],
+                     "quartets_per_s_fp64_build": st["quartets_kept"] / fb0["fp64"]
+                     if fb0["fp64"] else None,
                      "prim_quartets": st["prim_quartets_kept"],
                      "prim_pairs": st["prim_pairs_total"],
                      "dE_vs_oracle_Ha": {k: (v - oracle_ref["E_elec"]) if oracle_ref else None
@@ -456,6 +490,7 @@ def main():
     total_exec = sum(r["flops_exec"] for r in prof)
     total_ms = sum(r["ms"] for r in prof)
     traffic = kernel_traffic(a.workload, dom)
+    counters = kernel_counters(a.workload, dom)
 
     nq = st["quartets_kept"]
     out = {
@@ -505,7 +540,8 @@ def main():
                      "launches_timed": len(steps_prof),
                      "achieved_dense_model": achieved_model,
                      "frac_dense_model": achieved_model / FP64_PEAK_TFLOPS,
-                     "launch_flops_dense_model": dom["flops"]},
+                     "launch_flops_dense_model": dom["flops"],
+                     "rocprof_sq": counters},
         "class_profile": [{"cls": r["cls"], "ms": round(r["ms"], 4),
                            "quartets": r["quartets"],
                            "tflops": round(r["flops"] / max(r["ms"], 1e-9) / 1e9, 3),

@@ -50,8 +50,22 @@ def _per_dispatch(path):
     return list(agg.values())
 
 
+def _per_dispatch_counters(path):
+    """Per dispatch: kernel name, duration and every counter summed over its
+    instances."""
+    agg = collections.OrderedDict()
+    for r in csv.DictReader(open(path)):
+        k = int(r["Dispatch_Id"])
+        if k not in agg:
+            agg[k] = {"name": r["Kernel_Name"], "c": collections.Counter(),
+                      "ns": int(r["End_Timestamp"]) - int(r["Start_Timestamp"])}
+        agg[k]["c"][r["Counter_Name"]] += float(r["Counter_Value"])
+    return list(agg.values())
+
+
 def _class_of(name):
-    m = re.search(r"k_eri_(?:lane_ko|lane|wave)<(\d), (\d), (\d), (\d), (double|float)(, true)?", name)
+    m = re.search(r"k_eri_(?:lane_ko|lane|wave|mfma)<(\d), (\d), (\d), (\d), (double|float)(, true)?",
+                  name)
     if not m or m.group(6):      # stored-block (screening) launches are not Fock-build work
         return None
     la, lb, lc, ld = (int(m.group(i)) for i in range(1, 5))

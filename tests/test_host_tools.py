@@ -64,6 +64,49 @@ def test_bench_traffic_needs_matching_sources(monkeypatch):
     assert bench.kernel_traffic("water64", {"cls": "(pp|ps)"}) is None
 
 
+def test_sq_summary_counts_fp64_flops_per_lane(tmp_path):
+    """64 flops per FP64 ADD/MUL/TRANS wave instruction, 128 per FMA, 512
+    per FP64 MFMA MOPS, over the dispatch's duration; the longest launch of
+    a class is kept (the FP64 build's full list)."""
+    from paper_2510_24968_amd import prof_sq
+    seg = "void fsim::k_eri_lane_ko<1, 1, 1, 0, double, false, 3, 3, true>(fsim::EriArgs)"
+    sq = tmp_path / "sq.csv"
+    mix = tmp_path / "mix.csv"
+    with open(sq, "w", newline="") as f:
+        w = csv.DictWriter(f, fieldnames=FIELDS)
+        w.writeheader()
+        for cname, v in (("SQ_WAVE_CYCLES", 1000.0), ("SQ_WAIT_ANY", 250.0),
+                         ("SQ_ACTIVE_INST_VALU", 500.0)):
+            w.writerow({k: 0 for k in FIELDS} | {"Dispatch_Id": 1, "Kernel_Name": seg,
+                                                 "Counter_Name": cname, "Counter_Value": v,
+                                                 "Start_Timestamp": 0, "End_Timestamp": 2_000_000})
+    with open(mix, "w", newline="") as f:
+        w = csv.DictWriter(f, fieldnames=FIELDS)
+        w.writeheader()
+        for d, ns in ((1, 2_000_000), (2, 1_000_000)):     # a shorter second launch is ignored
+            for cname, v in (("SQ_INSTS_VALU_FMA_F64", 1e6), ("SQ_INSTS_VALU_ADD_F64", 2e6),
+                             ("SQ_INSTS_VALU_MFMA_MOPS_F64", 1e3)):
+                w.writerow({k: 0 for k in FIELDS} | {"Dispatch_Id": d, "Kernel_Name": seg,
+                                                     "Counter_Name": cname, "Counter_Value": v,
+                                                     "Start_Timestamp": 0, "End_Timestamp": ns})
+    r = prof_sq.summarise(str(sq), str(mix))["(pp|ps)"]
+    flops = 64 * (2e6 + 2 * 1e6) + 512 * 1e3
+    assert r["fp64_flops_issued"] == pytest.approx(flops)
+    assert r["fp64_tflops_issued"] == pytest.approx(flops / 2e-3 / 1e12)
+    assert r["wait"] == pytest.approx(0.25) and r["valu_busy"] == pytest.approx(0.5)
+
+
+def test_bench_counters_need_matching_sources(monkeypatch):
+    import bench
+    path = os.path.join(ROOT, "profiles", "k_eri_water64_fp64_sq_counters.md")
+    blob = json.loads(open(path).read().split("```json")[1].split("```")[0])
+    monkeypatch.setattr(prof_traffic, "source_digest", lambda: blob["source_digest"])
+    rec = bench.kernel_counters("water64", {"cls": "(pp|ps)"})
+    assert rec["fp64_tflops_issued"] == blob["kernels"]["(pp|ps)"]["fp64_tflops_issued"]
+    monkeypatch.setattr(prof_traffic, "source_digest", lambda: "0" * 16)
+    assert bench.kernel_counters("water64", {"cls": "(pp|ps)"}) is None
+
+
 class _FakeCtx:
     def __init__(self, recs):
         self.recs = recs
@@ -99,7 +142,7 @@ def test_committed_tuning_caches_are_well_formed():
         assert entries
         for key, e in entries.items():
             assert key == autotune.cache_key(e)
-            assert 0 <= e["variant"] < 7 and e["waves_per_block"] in (1, 2, 4)
+            assert 0 <= e["variant"] < 7 and e["waves_per_block"] in (1, 2, 4, 8)
 
 
 def test_cpu_baseline_samples_kept_quartets():

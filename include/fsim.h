@@ -373,8 +373,11 @@ fsim_status fsim_set_graph(fsim_ctx *ctx, int32_t enable);
  * tile code (d classes keep their own launches, so a C/H batch needs one
  * ERI launch per build and precision).  Per-launch profiling then reports
  * the persistent launch as one record with bra_class = ket_class = 6.  The
- * launch is captured in graphs like the others.  enable = 0 (default):
- * per-class launches with the tuned variants.  Drops captured graphs. */
+ * launch is captured in graphs like the others.  With fsim_set_krow_lds on
+ * (default) and segments averaging at least 16 tiles, the queue items are
+ * segments taken by whole blocks, which keep the bra's K' rows in LDS (if
+ * they fit); otherwise tile items taken by single waves.  enable = 0 (default): per-class launches with the tuned
+ * variants.  Drops captured graphs. */
 fsim_status fsim_set_persistent(fsim_ctx *ctx, int32_t enable);
 
 /* enable != 0 (default): lane-kernel launches tuned to segment mode
@@ -386,7 +389,8 @@ fsim_status fsim_set_persistent(fsim_ctx *ctx, int32_t enable);
  * builds cut their segments again for every build).  A launch whose rows
  * (ncart(l_a) + ncart(l_b) rows of N doubles, N the largest molecule) do
  * not fit in LDS next to the kernel's own use adds every K' term with a
- * global atomic instead, as enable = 0 does everywhere (segment-mode settings then run over tiles with 4 waves
+ * global atomic instead, as enable = 0 does everywhere.  The same holds for
+ * the persistent s/p launch (segment items) and the stored-integral digest (segment-mode settings then run over tiles with 4 waves
  * per block).  Results differ only in summation order.  Drops captured
  * graphs. */
 fsim_status fsim_set_krow_lds(fsim_ctx *ctx, int32_t enable);

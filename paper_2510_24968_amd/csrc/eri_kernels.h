@@ -290,31 +290,40 @@ __device__ __forceinline__ void digest_chunk(const T (&out)[(A1 - A0) * ncart(LB
 // b), so they are added into the block's LDS copy of those rows; after a
 // block barrier the non-zero entries go to global K' with one atomic each
 // and the rows are cleared.  krow: (NA + NB) rows of a.kn doubles.
+// The block's rows after segment sg: non-zero entries added to global K'
+// and cleared (every thread of the block takes part; no barriers inside).
+template <int NA, int NB>
+__device__ __forceinline__ void segment_flush(const EriArgs &a, double *__restrict__ krow,
+                                              long long xoff, int sg) {
+    constexpr int NR = NA + NB;
+    const int kn = a.kn;
+    const int bra = a.tl.bra[a.tl.seg_rec[sg]];
+    const int mol = a.bra.mol[bra];
+    const int N = a.mol_n[mol];
+    const int f1 = a.bra.bf1[bra], f2 = a.bra.bf2[bra];
+    double *__restrict__ Kh = a.Kh + xoff + a.mol_off[mol];
+    for (int x = threadIdx.x; x < NR * N; x += blockDim.x) {
+        const int r = x / N, col = x - r * N;
+        const double v = krow[r * kn + col];
+        if (v != 0.0) {
+            atomicAdd(&Kh[(size_t)(r < NA ? f1 + r : f2 + r - NA) * N + col], v);
+            krow[r * kn + col] = 0.0;
+        }
+    }
+}
+
 template <int NA, int NB, typename Body>
 __device__ __forceinline__ void run_segments(const EriArgs &a, double *__restrict__ krow,
                                              long long xoff, Body &&body) {
     constexpr int NR = NA + NB;
     const int wave = threadIdx.x >> 6, wpb = blockDim.x >> 6;
-    const int kn = a.kn;
-    for (int x = threadIdx.x; x < NR * kn; x += blockDim.x) krow[x] = 0.0;
+    for (int x = threadIdx.x; x < NR * a.kn; x += blockDim.x) krow[x] = 0.0;
     __syncthreads();
     for (int sg = blockIdx.x; sg < a.tl.nseg; sg += gridDim.x) {
         const int t0 = a.tl.seg_t0[sg], nt = a.tl.seg_nt[sg];
         for (int t = t0 + wave; t < t0 + nt; t += wpb) body(__builtin_amdgcn_readfirstlane(t));
         __syncthreads();
-        const int bra = a.tl.bra[a.tl.seg_rec[sg]];
-        const int mol = a.bra.mol[bra];
-        const int N = a.mol_n[mol];
-        const int f1 = a.bra.bf1[bra], f2 = a.bra.bf2[bra];
-        double *__restrict__ Kh = a.Kh + xoff + a.mol_off[mol];
-        for (int x = threadIdx.x; x < NR * N; x += blockDim.x) {
-            const int r = x / N, col = x - r * N;
-            const double v = krow[r * kn + col];
-            if (v != 0.0) {
-                atomicAdd(&Kh[(size_t)(r < NA ? f1 + r : f2 + r - NA) * N + col], v);
-                krow[r * kn + col] = 0.0;
-            }
-        }
+        segment_flush<NA, NB>(a, krow, xoff, sg);
         __syncthreads();
     }
 }

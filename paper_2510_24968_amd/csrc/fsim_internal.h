@@ -213,7 +213,7 @@ hipError_t launch_one_electron_impl(const ShellsDev &sh, const double *boys, int
 template <int X, int Y, bool F32>
 hipError_t launch_eri_unit(bool store, int variant, int wpb, const EriArgs &a, hipStream_t s);
 // Persistent launch over the s/p quartet classes (persistent.hip): queue
-// slot k holds the tiles of class (persist_bra(k) | persist_ket(k)), slots
+// slot k holds the tiles (or segments) of class (persist_bra(k) | persist_ket(k)), slots
 // 0..5 = (pp|pp) (pp|ps) (ps|ps) (pp|ss) (ps|ss) (ss|ss); start[k] is the
 // first queue position of slot k, start[6] the total.  *counter must be 0
 // at launch.  Every slot's stage_prims x (4 + n_entries) FP64/T values must
@@ -226,6 +226,11 @@ struct PersistArgs {
     int *counter;
     int stage_bytes;
     const double *boys;
+    // > 0: queue items are segments (start[] counts segments), each taken
+    // by a whole block that keeps its bra's K' rows in LDS (kn doubles per
+    // row, as EriArgs::kn, which every slot's record carries too); 0: items
+    // are tiles taken by single waves, K' terms added globally
+    int kn;
 };
 hipError_t launch_persistent(bool fp32, const PersistArgs &p, hipStream_t s);
 // digest of stored blocks (stored.hip): a.out = the class's store, a.tl its

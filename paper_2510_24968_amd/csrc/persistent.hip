@@ -92,6 +92,26 @@ __device__ __forceinline__ void persist_tile(const PersistArgs &p, int tile, con
         p.cls[SLOT], tile, bp, sp);
 }
 
+// Segment item: the block's waves split the segment's tiles, adding K' into
+// the LDS rows, which are flushed once the block is done with it.
+template <int SLOT, typename T, typename BP>
+__device__ __forceinline__ void persist_segment(const PersistArgs &p, int sg, const BP &bp,
+                                                double *sp, double *krow) {
+    constexpr int X = persist_bra(SLOT), Y = persist_ket(SLOT);
+    constexpr int LA = pc_l1(X), LB = pc_l2(X), LC = pc_l1(Y), LD = pc_l2(Y);
+    constexpr int B = PERSIST_BUDGET;
+    const EriArgs &a = p.cls[SLOT];
+    const int wave = threadIdx.x >> 6, wpb = blockDim.x >> 6;
+    const int t0 = a.tl.seg_t0[sg], nt = a.tl.seg_nt[sg];
+    for (int t = t0 + wave; t < t0 + nt; t += wpb)
+        ko_tile<LA, LB, LC, LD, T, false, chunk_a(LA, LB, LC, LD, B), chunk_cd(LA, LB, LC, LD, B)>(
+            a, __builtin_amdgcn_readfirstlane(t), bp, sp, krow, true);
+    __syncthreads();
+    const long long xoff = a.xcd_stride ? xcd_index() * a.xcd_stride : 0;
+    segment_flush<ncart(LA), ncart(LB)>(a, krow, xoff, sg);
+    __syncthreads();
+}
+
 template <typename T>
 __global__ __launch_bounds__(256, 2) void k_eri_persistent(PersistArgs p) {
     constexpr bool F32 = std::is_same<T, float>::value;
@@ -106,6 +126,32 @@ __global__ __launch_bounds__(256, 2) void k_eri_persistent(PersistArgs p) {
     using BP = std::conditional_t<F32, BoysRawMixed, BoysRaw64>;
     const BP bp{tab};
     const int total = p.start[PERSIST_SLOTS];
+    if (p.kn > 0) {
+        // segment items, one per block at a time; the rows (6 of kn doubles,
+        // the pp bras' count) follow the 4 staging slices
+        double *__restrict__ krow = (double *)(stage_lds + (size_t)4 * p.stage_bytes);
+        __shared__ int item;
+        for (int x = threadIdx.x; x < 6 * p.kn; x += blockDim.x) krow[x] = 0.0;
+        while (true) {
+            __syncthreads();   // the rows are clear and every thread has read the last item
+            if (threadIdx.x == 0) item = atomicAdd(p.counter, 1);
+            __syncthreads();
+            const int q = item;
+            if (q >= total) break;   // the same q in every thread of the block
+            int slot = 0;
+            while (slot + 1 < PERSIST_SLOTS && q >= p.start[slot + 1]) ++slot;
+            const int sg = q - p.start[slot];
+            switch (slot) {
+                case 0: persist_segment<0, T>(p, sg, bp, sp, krow); break;
+                case 1: persist_segment<1, T>(p, sg, bp, sp, krow); break;
+                case 2: persist_segment<2, T>(p, sg, bp, sp, krow); break;
+                case 3: persist_segment<3, T>(p, sg, bp, sp, krow); break;
+                case 4: persist_segment<4, T>(p, sg, bp, sp, krow); break;
+                default: persist_segment<5, T>(p, sg, bp, sp, krow); break;
+            }
+        }
+        return;
+    }
     while (true) {
         int q = 0;
         if (lane == 0) q = atomicAdd(p.counter, 1);
@@ -125,30 +171,47 @@ __global__ __launch_bounds__(256, 2) void k_eri_persistent(PersistArgs p) {
     }
 }
 
-hipError_t launch_persistent(bool fp32, const PersistArgs &p, hipStream_t s) {
-    if (p.start[PERSIST_SLOTS] <= 0) return hipSuccess;
+hipError_t launch_persistent(bool fp32, const PersistArgs &pin, hipStream_t s) {
+    if (pin.start[PERSIST_SLOTS] <= 0) return hipSuccess;
+    PersistArgs p = pin;
+    if (p.kn > 0) {
+        // segment items need the rows beside the Boys grid and the staging
+        // slices; otherwise tile items with global K' atomics
+        const size_t stat = (size_t)BOYS_NT * (fp32 ? PERSIST_NR32 * sizeof(float)
+                                                    : PERSIST_NR * sizeof(double));
+        const size_t need_lds =
+            stat + (size_t)4 * p.stage_bytes + (size_t)6 * p.kn * sizeof(double);
+        if (need_lds > LDS_PER_CU) {
+            p.kn = 0;
+            for (int k = 0; k < PERSIST_SLOTS; ++k) {
+                p.cls[k].kn = 0;
+                p.start[k + 1] = p.start[k] + p.cls[k].tl.ntile;
+            }
+        }
+    }
     // resident grid: as many blocks as fit on the device at once (queried
     // once per kernel and LDS size), never more than one per 4 tiles
-    static int cached[2][2] = {{0, 0}, {0, 0}};   // [fp32] -> (stage_bytes, blocks per CU)
+    static int cached[2][2] = {{0, 0}, {0, 0}};   // [fp32] -> (dynamic LDS, blocks per CU)
     int dev = 0, ncu = 0;
     hipError_t e = hipGetDevice(&dev);
     if (e != hipSuccess) return e;
     e = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
     if (e != hipSuccess) return e;
-    const size_t dyn = (size_t)4 * p.stage_bytes;
+    const size_t dyn = (size_t)4 * p.stage_bytes + (size_t)6 * p.kn * sizeof(double);
     int per_cu = 0;
-    if (cached[fp32][0] == p.stage_bytes && cached[fp32][1] > 0) {
+    if (cached[fp32][0] == (int)dyn && cached[fp32][1] > 0) {
         per_cu = cached[fp32][1];
     } else {
         e = fp32 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_eri_persistent<float>, 256, dyn)
                  : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_eri_persistent<double>, 256, dyn);
         if (e != hipSuccess) return e;
         if (per_cu < 1) per_cu = 1;
-        cached[fp32][0] = p.stage_bytes;
+        cached[fp32][0] = (int)dyn;
         cached[fp32][1] = per_cu;
     }
     int blocks = per_cu * ncu;
-    const int need = (p.start[PERSIST_SLOTS] + 3) / 4;
+    // tile items: one per wave; segment items: one per block
+    const int need = p.kn > 0 ? p.start[PERSIST_SLOTS] : (p.start[PERSIST_SLOTS] + 3) / 4;
     if (blocks > need) blocks = need;
     if (fp32)
         hipLaunchKernelGGL(k_eri_persistent<float>, dim3(blocks), dim3(256), dyn, s, p);

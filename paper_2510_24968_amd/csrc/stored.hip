@@ -33,8 +33,10 @@ __host__ __device__ constexpr int digest_chunk_a(int la, int lb, int lc, int ld)
     return ca;
 }
 
-template <int LA, int LB, int LC, int LD>
-__global__ __launch_bounds__(256) void k_digest_stored(EriArgs a) {
+// SEG: segment mode as in the lane kernels (blocks of 8 waves over segments
+// of one bra's tiles, the bra's K' rows in LDS, a.kn doubles per row).
+template <int LA, int LB, int LC, int LD, bool SEG>
+__global__ __launch_bounds__(SEG ? 512 : 256) void k_digest_stored(EriArgs a) {
     constexpr int NA = ncart(LA), NB = ncart(LB), NC = ncart(LC), ND = ncart(LD);
     constexpr int NCD = NC * ND, NE = NA * NB * NCD;
     constexpr int CA = digest_chunk_a(LA, LB, LC, LD), CDC = digest_chunk_cd(LA, LB, LC, LD);
@@ -42,9 +44,8 @@ __global__ __launch_bounds__(256) void k_digest_stored(EriArgs a) {
     const int lane = threadIdx.x & 63;
     const int wpb = blockDim.x >> 6;
     const long long xoff = a.xcd_stride ? xcd_index() * a.xcd_stride : 0;
-    for (int tile0 = blockIdx.x * wpb + (threadIdx.x >> 6); tile0 < a.tl.ntile;
-         tile0 += gridDim.x * wpb) {
-        const int tile = __builtin_amdgcn_readfirstlane(tile0);
+    auto tile_body = [&](const int tile, double *__restrict__ krow,
+                         const bool kl) __attribute__((always_inline)) {
         const int b = tile_bra(a.tl, tile);
         const int bra = __builtin_amdgcn_readfirstlane(a.tl.bra[b]);
         const int k0 = a.tl.ket_lo[b] + (tile - a.tl.tile_start[b]) * TILE;
@@ -81,19 +82,45 @@ __global__ __launch_bounds__(256) void k_digest_stored(EriArgs a) {
                 });
             });
             digest_chunk<LA, LB, LC, LD, double, A0, A1, CD0, CD1>(out, D, Jh, Kh, N, f1, f2, f3,
-                                                                   f4, fac, active);
+                                                                   f4, fac, active, krow, a.kn,
+                                                                   kl);
         });
+    };
+    if constexpr (SEG) {
+        extern __shared__ __align__(16) unsigned char row_lds[];
+        double *__restrict__ krow = (double *)row_lds;
+        run_segments<NA, NB>(a, krow, xoff, [&](int t) __attribute__((always_inline)) {
+            tile_body(t, krow, true);
+        });
+    } else {
+        for (int tile0 = blockIdx.x * wpb + (threadIdx.x >> 6); tile0 < a.tl.ntile;
+             tile0 += gridDim.x * wpb)
+            tile_body(__builtin_amdgcn_readfirstlane(tile0), nullptr, false);
     }
 }
 
 template <int X, int Y>
 static hipError_t launch_digest(int wpb, const EriArgs &a, hipStream_t s) {
     if (a.tl.ntile <= 0) return hipSuccess;
+    constexpr int LA = pc_l1(X), LB = pc_l2(X), LC = pc_l1(Y), LD = pc_l2(Y);
+    if (a.kn > 0 && a.tl.nseg > 0) {
+        EriArgs b = a;
+        b.stage_bytes = 0;
+        int blocks = 0;
+        size_t dyn = 0;
+        auto seg = k_digest_stored<LA, LB, LC, LD, true>;
+        if (segment_fit<LA, LB>((const void *)seg, 8, b, blocks, dyn)) {
+            hipLaunchKernelGGL(seg, dim3(blocks), dim3(512), dyn, s, b);
+            return hipGetLastError();
+        }
+    }
     if (wpb < 1 || wpb > 4) wpb = 4;
     int blocks = (a.tl.ntile + wpb - 1) / wpb;
     if (blocks > 8192) blocks = 8192;
-    hipLaunchKernelGGL((k_digest_stored<pc_l1(X), pc_l2(X), pc_l1(Y), pc_l2(Y)>), dim3(blocks),
-                       dim3(64 * wpb), 0, s, a);
+    EriArgs b = a;
+    b.kn = 0;
+    hipLaunchKernelGGL((k_digest_stored<LA, LB, LC, LD, false>), dim3(blocks), dim3(64 * wpb), 0,
+                       s, b);
     return hipGetLastError();
 }
 

@@ -546,6 +546,24 @@ def test_krow_lds_segments_water16():
                 print(f"water16 variant {variant} {prec} {'JK'[k]}: LDS rows vs global atomics "
                       f"{d:.2e}", flush=True)
                 assert d < 1e-11
+    # the persistent s/p launch: 22 tiles per segment here, so its queue
+    # items are segments (fewer items than the per-class launches' tiles)
+    ctx.set_krow_lds(True)
+    ctx.set_profiling(True)
+    ctx.fock_build(D, precision="fp64", want_jk=True)
+    sp_tiles = sum(r["tiles"] for r in ctx.class_profile() if r["bra_class"] <= 2)
+    ctx.set_persistent(True)
+    for prec in ("fp64", "mixed"):
+        r = ctx.fock_build(D, precision=prec, want_jk=True)
+        items = [p["tiles"] for p in ctx.class_profile() if p["bra_class"] == 6]
+        for k, M in enumerate((r["J"], r["K"])):
+            d = torch.max(torch.abs(M - res[False, prec][k])).item()
+            print(f"water16 persistent {prec} {'JK'[k]}: {d:.2e} (items {items})", flush=True)
+            assert d < 1e-11
+        if prec == "fp64":
+            assert items[0] < sp_tiles / 8
+    ctx.set_persistent(False)
+    ctx.set_profiling(False)
     rng = np.random.default_rng(16)
     mus, nus = rng.integers(0, ctx.nbf, 40), rng.integers(0, ctx.nbf, 40)
     Je, Ke = oracle.Basis(b).jk_elements(D.cpu().numpy(), mus, nus, tau=1e-11)
@@ -630,16 +648,18 @@ def test_batch_jk_matches_oracle_per_molecule():
         assert np.max(np.abs(Ks[k].cpu().numpy() - Ko)) < 1e-11, k
 
 
-@pytest.mark.parametrize("persistent", [False, True])
-def test_persistent_launch_matches_oracle(persistent):
-    """The s/p classes in one persistent queue launch (or per class): a small
-    batch of C/H molecules, a water molecule and an H chain, FP64 and with
-    every quartet an FP32 tile, J and K per molecule against the oracle; and
-    a water trimer, whose d classes keep their own launches."""
+@pytest.mark.parametrize("persistent,krow", [(False, True), (True, True), (True, False)])
+def test_persistent_launch_matches_oracle(persistent, krow):
+    """The s/p classes in one persistent queue launch (segment items that
+    keep K' rows in LDS, or tile items with global K' atomics) or per class:
+    a small batch of C/H molecules, a water molecule and an H chain, FP64
+    and with every quartet an FP32 tile, J and K per molecule against the
+    oracle; and a water trimer, whose d classes keep their own launches."""
     mols = _small_batch()
     for tf32, tol in ((0.0, 1e-11), (1e6, None)):
         bt = _fsim().Batch(mols, tau_fp32=tf32)
         bt.set_persistent(persistent)
+        bt.set_krow_lds(krow)
         bt.schwarz_screen(tau=0.0)
         blocks = [_random_density(synth.nbf_of(b), 40 + k) for k, b in enumerate(mols)]
         r = bt.fock_build(bt.pack([_dev(x) for x in blocks]),
@@ -654,6 +674,7 @@ def test_persistent_launch_matches_oracle(persistent):
     b = synth.water_cluster(3, 2)
     ctx = _ctx(b, tau=1e-10)
     ctx.set_persistent(persistent)
+    ctx.set_krow_lds(krow)
     ctx.schwarz_screen()
     D = _random_density(ctx.nbf, 8)
     Jo, Ko = oracle.Basis(b).fock_jk(D, tau=1e-10)
@@ -692,7 +713,10 @@ def test_ch1024_persistent_graph_one_launch():
         assert len(prof) == (1 if p == "fp64" else 2) and all(r["bra_class"] == 6 for r in prof)
         print(f"ch1024 persistent {p}: {[round(r['ms'], 2) for r in prof]} ms, "
               f"max |dF| = {torch.max(torch.abs(F - ref[p])).item():.2e}", flush=True)
-        assert torch.max(torch.abs(F - ref[p])).item() < 1e-10
+        # FP64: rounding order only; mixed: the tuned per-class FP32 kernels and
+        # the persistent launch's ket-outer bodies round the FP32 tiles (bounds
+        # below 1e-5) at different points, about 1e-7 of each tile's share
+        assert torch.max(torch.abs(F - ref[p])).item() < (1e-10 if p == "fp64" else 1e-8)
     bt.set_profiling(False)
     bt.set_graph(True)
     for rep in range(3):

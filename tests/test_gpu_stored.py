@@ -80,7 +80,9 @@ def test_stored_scf_water10_and_rescreen():
     D = r["D"]
     e64 = ctx.fock_build(D, "fp64")["E_elec"]
     emx = ctx.fock_build(D, "mixed")["E_elec"]
-    assert e64 == emx                     # both digest the same FP64 store
+    # both digest the same FP64 store (the atomics' order differs between
+    # builds; FP32 tiles would move the energy by ~1e-9 Ha)
+    assert abs(e64 - emx) < 1e-11
     ctx.schwarz_screen()                  # drops the store: direct builds again
     e_direct = ctx.fock_build(D, "fp64")["E_elec"]
     assert abs(e_direct - e64) < 1e-9

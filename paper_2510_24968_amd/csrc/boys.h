@@ -36,9 +36,27 @@ __device__ inline void boys_stage(double *lds, const double *__restrict__ g, int
     }
 }
 
-// F_0..F_L at T from a table staged for order L.
+// Large-T branch shared by the evaluators: F_0 = sqrt(pi)/2 / sqrt(T) and
+// the upward recursion with 1/(2T) taken from the same reciprocal square
+// root (a product of two roundings instead of a division).
+template <int L>
+__device__ __forceinline__ void boys_large_t(double T, double e, double *F) {
+    const double rs = rsqrt(T);
+    F[0] = 0.88622692545275801365 * rs;
+    if constexpr (L > 0) {
+        const double h = 0.5 * rs * rs;
+#pragma unroll
+        for (int n = 0; n < L; ++n) F[n + 1] = ((2 * n + 1) * F[n] - e) * h;
+    }
+}
+
+// F_0..F_L at T from a table staged for order L.  exp(-T), which both
+// branches need for L > 0, is evaluated once ahead of the branch: the lanes
+// of a wave often take both branches, which would otherwise run it twice.
 template <int L>
 __device__ __forceinline__ void boys_eval(double T, const double *tab, double *F) {
+    double e = 0.0;
+    if constexpr (L > 0) e = exp(-T);
     if (T < BOYS_TMAX) {
         const int k = __double2int_rn(T * BOYS_INV_DT);
         const double d = k * BOYS_DT - T;
@@ -48,17 +66,12 @@ __device__ __forceinline__ void boys_eval(double T, const double *tab, double *F
         for (int j = BOYS_NTAYLOR - 2; j >= 0; --j) f = fma(f, d, c[j]);
         F[L] = f;
         if constexpr (L > 0) {
-            const double e = exp(-T), t2 = 2.0 * T;
+            const double t2 = 2.0 * T;
 #pragma unroll
             for (int n = L; n > 0; --n) F[n - 1] = fma(t2, F[n], e) * (1.0 / (2 * n - 1));
         }
     } else {
-        F[0] = 0.88622692545275801365 * rsqrt(T);   // sqrt(pi)/2 / sqrt(T)
-        if constexpr (L > 0) {
-            const double e = exp(-T), h = 0.5 / T;
-#pragma unroll
-            for (int n = 0; n < L; ++n) F[n + 1] = ((2 * n + 1) * F[n] - e) * h;
-        }
+        boys_large_t<L>(T, e, F);
     }
 }
 
@@ -83,6 +96,8 @@ __device__ inline void boys_stage32(float *lds, const double *__restrict__ g, in
 
 template <int L>
 __device__ __forceinline__ void boys_eval_mixed(double T, const float *tab, double *F) {
+    double e = 0.0;
+    if constexpr (L > 0) e = exp(-T);
     if (T < BOYS_TMAX) {
         const float Tf = (float)T;
         const int k = __float2int_rn(Tf * (float)BOYS_INV_DT);
@@ -93,17 +108,12 @@ __device__ __forceinline__ void boys_eval_mixed(double T, const float *tab, doub
         for (int j = BOYS_NTAYLOR32 - 2; j >= 0; --j) f = fmaf(f, d, c[j]);
         F[L] = (double)f;
         if constexpr (L > 0) {
-            const double e = exp(-T), t2 = 2.0 * T;
+            const double t2 = 2.0 * T;
 #pragma unroll
             for (int n = L; n > 0; --n) F[n - 1] = fma(t2, F[n], e) * (1.0 / (2 * n - 1));
         }
     } else {
-        F[0] = 0.88622692545275801365 * rsqrt(T);   // sqrt(pi)/2 / sqrt(T)
-        if constexpr (L > 0) {
-            const double e = exp(-T), h = 0.5 / T;
-#pragma unroll
-            for (int n = 0; n < L; ++n) F[n + 1] = ((2 * n + 1) * F[n] - e) * h;
-        }
+        boys_large_t<L>(T, e, F);
     }
 }
 

@@ -18,6 +18,8 @@ struct BoysRaw64 {
     template <int L>
     __device__ __forceinline__ void eval(double T, double *F) const {
         static_assert(L + BOYS_NTAYLOR <= PERSIST_NR, "order outside the persistent grid");
+        double e = 0.0;
+        if constexpr (L > 0) e = exp(-T);
         if (T < BOYS_TMAX) {
             const int k = __double2int_rn(T * BOYS_INV_DT);
             const double d = k * BOYS_DT - T;
@@ -27,17 +29,12 @@ struct BoysRaw64 {
             for (int j = BOYS_NTAYLOR - 2; j >= 0; --j) f = fma(f, d, c[j] * inv_factorial(j));
             F[L] = f;
             if constexpr (L > 0) {
-                const double e = exp(-T), t2 = 2.0 * T;
+                const double t2 = 2.0 * T;
 #pragma unroll
                 for (int n = L; n > 0; --n) F[n - 1] = fma(t2, F[n], e) * (1.0 / (2 * n - 1));
             }
         } else {
-            F[0] = 0.88622692545275801365 * rsqrt(T);
-            if constexpr (L > 0) {
-                const double e = exp(-T), h = 0.5 / T;
-#pragma unroll
-                for (int n = 0; n < L; ++n) F[n + 1] = ((2 * n + 1) * F[n] - e) * h;
-            }
+            boys_large_t<L>(T, e, F);
         }
     }
 };
@@ -48,6 +45,8 @@ struct BoysRawMixed {
     template <int L>
     __device__ __forceinline__ void eval(double T, double *F) const {
         static_assert(L + BOYS_NTAYLOR32 <= PERSIST_NR32, "order outside the persistent grid");
+        double e = 0.0;
+        if constexpr (L > 0) e = exp(-T);
         if (T < BOYS_TMAX) {
             const float Tf = (float)T;
             const int k = __float2int_rn(Tf * (float)BOYS_INV_DT);
@@ -59,17 +58,12 @@ struct BoysRawMixed {
                 f = fmaf(f, d, c[j] * (float)inv_factorial(j));
             F[L] = (double)f;
             if constexpr (L > 0) {
-                const double e = exp(-T), t2 = 2.0 * T;
+                const double t2 = 2.0 * T;
 #pragma unroll
                 for (int n = L; n > 0; --n) F[n - 1] = fma(t2, F[n], e) * (1.0 / (2 * n - 1));
             }
         } else {
-            F[0] = 0.88622692545275801365 * rsqrt(T);
-            if constexpr (L > 0) {
-                const double e = exp(-T), h = 0.5 / T;
-#pragma unroll
-                for (int n = 0; n < L; ++n) F[n + 1] = ((2 * n + 1) * F[n] - e) * h;
-            }
+            boys_large_t<L>(T, e, F);
         }
     }
 };

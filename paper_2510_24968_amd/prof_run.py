@@ -24,6 +24,9 @@ def main():
                     help="diag: 0.01 I (the build evaluates every kept quartet whatever the "
                          "density, so the kernels' work is the same and no eigensolver "
                          "dispatches run under the counters); core: the core-Hamiltonian guess")
+    ap.add_argument("--stored", action="store_true",
+                    help="compute the kept quartets once into the store (fsim_store_eris) and "
+                         "time builds that digest it")
     ap.add_argument("--tau-prim", type=float, default=None,
                     help="primitive-pair screening threshold (default 1e-4 x the Schwarz tau, "
                          "as the benchmark runs; 0: every primitive pair)")
@@ -57,6 +60,8 @@ def main():
     else:
         D = 0.01 * torch.eye(ctx.nbf, dtype=torch.float64, device="cuda")
     torch.cuda.synchronize()
+    if a.stored:
+        log(f"stored integrals: {ctx.store_eris() / 1e9:.2f} GB")
     log(f"density ready ({a.density}); Fock builds follow")
     for k in range(a.builds):
         t0 = time.time()

@@ -293,14 +293,17 @@ fsim_status fsim_get_class_profile(fsim_ctx *ctx, fsim_class_profile *out, int32
  * fsim_set_krow_lds: blocks of 8 waves, or 4 for kernels held to one wave
  * per SIMD, over segments of one bra's tiles with the bra's K' rows in LDS;
  * launches whose rows do not fit run over tiles with 4 waves per block).
- * The default is variant 1 in segment mode. */
+ * The default is variant 1 in segment mode with 64 tiles per segment;
+ * seg_tiles sets the segment length per class and precision (fsim_autotune
+ * times 32, 64, 128 and 256 for the classes that choose segment mode). */
 typedef struct {
     int32_t bra_class, ket_class;   /* pair classes, bra >= ket */
     int32_t fp32;
     int32_t variant;
     int32_t waves_per_block;
     int32_t kbra, kket;             /* max primitive pairs of the classes (cache key) */
-    int32_t pad;
+    int32_t seg_tiles;              /* segment mode: tiles per segment, a power of 2 in
+                                       16..512; 0 in fsim_set_tuning: 64 */
     double ms;                      /* measured time of the chosen setting (autotune) */
 } fsim_tuning;
 
@@ -381,8 +384,8 @@ fsim_status fsim_set_graph(fsim_ctx *ctx, int32_t enable);
 fsim_status fsim_set_persistent(fsim_ctx *ctx, int32_t enable);
 
 /* enable != 0 (default): lane-kernel launches tuned to segment mode
- * (waves_per_block = 8) take whole
- * segments of up to 64 tiles of one bra pair per workgroup and add the
+ * (waves_per_block = 8) take whole segments of up to seg_tiles (64 by
+ * default, see fsim_tuning) tiles of one bra pair per workgroup and add the
  * quartets' K' terms, which all lie in the rows of the bra's functions
  * (Eq. fock: K'_ac, K'_ad, K'_bc, K'_bd), into an LDS copy of those rows;
  * the non-zero entries go to global K' once per segment (incremental

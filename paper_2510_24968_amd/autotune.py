@@ -38,7 +38,7 @@ def tune(ctx, D, precisions=("mixed", "fp64"), progress=True):
             if rec["ms"] > 0 and bool(rec["fp32"]) == (prec == "mixed"):
                 table[cache_key(rec)] = {k: rec[k] for k in
                                          ("cls", "bra_class", "ket_class", "fp32", "variant",
-                                          "waves_per_block", "kbra", "kket", "ms")}
+                                          "waves_per_block", "seg_tiles", "kbra", "kket", "ms")}
     apply(ctx, table)
     return table
 
@@ -65,7 +65,7 @@ def apply(ctx, table):
         if hit is not None:
             recs.append(dict(bra_class=r["bra_class"], ket_class=r["ket_class"], fp32=r["fp32"],
                              variant=hit["variant"], waves_per_block=hit["waves_per_block"],
-                             ms=hit.get("ms", 0.0)))
+                             seg_tiles=hit.get("seg_tiles", 0), ms=hit.get("ms", 0.0)))
     if recs:
         ctx.set_tuning(recs)
     return len(recs)
@@ -98,7 +98,7 @@ def main():
     print(f"tuned {len(table)} class settings in {time.time() - t0:.1f}s", file=sys.stderr)
     out = a.out or os.path.join(os.getcwd(), f"tuning_{a.workload}.json")
     save(table, out, {"workload": a.workload, "device": "MI355X (gfx950)", "tau_prim": tau_prim})
-    print(json.dumps({k: (v["variant"], v["waves_per_block"], round(v["ms"], 3))
+    print(json.dumps({k: (v["variant"], v["waves_per_block"], v.get("seg_tiles", 0), round(v["ms"], 3))
                       for k, v in sorted(table.items())}))
 
 

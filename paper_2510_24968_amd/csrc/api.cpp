@@ -71,7 +71,28 @@ struct ClassLists {
     std::vector<int> dstart[3], dhi[3];
     std::vector<int> dseg[3];   // segments of the delta lists: rec, t0, nt (3 arrays)
     int64_t dnq[3] = {0, 0, 0};
+    // device capacity of each list's segment arrays (segments of the
+    // smallest segment size, SEG_MIN tiles)
+    int segcap[3] = {0, 0, 0};
 };
+
+// Segment sizes the tuning may choose (tiles per segment).
+constexpr int SEG_MIN = 16, SEG_MAX = 512;
+static bool valid_seg(int n) { return n >= SEG_MIN && n <= SEG_MAX && (n & (n - 1)) == 0; }
+
+// Segments of at most seg tiles over the tile ranges of a list's bra records
+// (tile starts st[0..nbra]) into host arrays rec/t0/nt; returns the count.
+static size_t cut_segments(const std::vector<int> &st, int seg, int *rec, int *t0, int *nt) {
+    size_t ns = 0;
+    for (size_t r = 0; r + 1 < st.size(); ++r)
+        for (int t = st[r]; t < st[r + 1]; t += seg) {
+            rec[ns] = (int)r;
+            t0[ns] = t;
+            nt[ns] = std::min(seg, st[r + 1] - t);
+            ++ns;
+        }
+    return ns;
+}
 
 struct DevPool {
     std::vector<void *> ptrs;
@@ -131,6 +152,8 @@ struct fsim_ctx {
     // lane-kernel launches accumulate each bra's K' rows in LDS over
     // segments of its tiles (default), or add every K' term globally
     bool krow_lds = true;
+    // tiles per segment, per class and precision (tuning)
+    int segt[NPCLASS][NPCLASS][2];
     // captured Fock build (hipGraph), one per precision
     bool graph_enabled = false;
     hipStream_t gstream = nullptr;
@@ -487,6 +510,7 @@ static fsim_status create_impl(const fsim_basis *mols, int nmol, const fsim_opti
             for (int f = 0; f < 2; ++f) {
                 c->variant[X][Y][f] = ERI_DEFAULT_VARIANT;
                 c->wpb[X][Y][f] = 8;
+                c->segt[X][Y][f] = SEG_TILES;
                 c->tuned_ms[X][Y][f] = 0.0;
             }
     c->nmol = nmol;
@@ -965,7 +989,8 @@ static FlopModel flop_model_exec(int la, int lb, int lc, int ld) {
 }
 
 static fsim_status upload_list(DevPool &pool, TileList &tl, const std::vector<int> &bra,
-                               const std::vector<int> &lo, const std::vector<int> &hi) {
+                               const std::vector<int> &lo, const std::vector<int> &hi, int seg,
+                               int *segcap) {
     tl = TileList{};
     tl.nbra = (int)bra.size();
     std::vector<int> start(bra.size() + 1, 0);
@@ -988,22 +1013,28 @@ static fsim_status upload_list(DevPool &pool, TileList &tl, const std::vector<in
     HIPCHK(hipMemcpy(tl.bra, bra.data(), sizeof(int) * bra.size(), hipMemcpyHostToDevice));
     HIPCHK(hipMemcpy(tl.ket_lo, lo.data(), sizeof(int) * bra.size(), hipMemcpyHostToDevice));
     HIPCHK(hipMemcpy(tl.ket_hi, hi.data(), sizeof(int) * bra.size(), hipMemcpyHostToDevice));
-    // segments of at most SEG_TILES tiles, each within one bra record
-    std::vector<int> srec, st0, snt;
-    for (size_t i = 0; i < bra.size(); ++i)
-        for (int t = start[i]; t < start[i + 1]; t += SEG_TILES) {
-            srec.push_back((int)i);
-            st0.push_back(t);
-            snt.push_back(std::min(SEG_TILES, start[i + 1] - t));
-        }
-    tl.nseg = (int)srec.size();
-    HIPCHK(pool.alloc(&tl.seg_rec, srec.size()));
-    HIPCHK(pool.alloc(&tl.seg_t0, st0.size()));
-    HIPCHK(pool.alloc(&tl.seg_nt, snt.size()));
-    HIPCHK(hipMemcpy(tl.seg_rec, srec.data(), sizeof(int) * srec.size(), hipMemcpyHostToDevice));
-    HIPCHK(hipMemcpy(tl.seg_t0, st0.data(), sizeof(int) * st0.size(), hipMemcpyHostToDevice));
-    HIPCHK(hipMemcpy(tl.seg_nt, snt.data(), sizeof(int) * snt.size(), hipMemcpyHostToDevice));
+    // segments of at most seg tiles, each within one bra record; the device
+    // arrays hold the segments of the smallest size, so that a later tuning
+    // may cut them again (set_segments)
+    size_t cap = 0;
+    for (size_t i = 0; i < bra.size(); ++i) cap += (start[i + 1] - start[i] + SEG_MIN - 1) / SEG_MIN;
+    *segcap = (int)cap;
+    std::vector<int> h(3 * cap);
+    tl.nseg = (int)cut_segments(start, seg, h.data(), h.data() + cap, h.data() + 2 * cap);
+    HIPCHK(pool.alloc(&tl.seg_rec, cap));
+    HIPCHK(pool.alloc(&tl.seg_t0, cap));
+    HIPCHK(pool.alloc(&tl.seg_nt, cap));
+    HIPCHK(hipMemcpy(tl.seg_rec, h.data(), sizeof(int) * tl.nseg, hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(tl.seg_t0, h.data() + cap, sizeof(int) * tl.nseg, hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(tl.seg_nt, h.data() + 2 * cap, sizeof(int) * tl.nseg, hipMemcpyHostToDevice));
     return FSIM_OK;
+}
+
+// Tile starts of a host list (bra records with ket ranges [lo, hi)).
+static std::vector<int> tile_starts(const std::vector<int> &lo, const std::vector<int> &hi) {
+    std::vector<int> st(lo.size() + 1, 0);
+    for (size_t i = 0; i < lo.size(); ++i) st[i + 1] = st[i] + (hi[i] - lo[i] + TILE - 1) / TILE;
+    return st;
 }
 
 extern "C" fsim_status fsim_schwarz_screen(fsim_ctx *c, double tau, double tau32, double *Q_out,
@@ -1173,9 +1204,12 @@ extern "C" fsim_status fsim_schwarz_screen(fsim_ctx *c, double tau, double tau32
                 S.quartets_fp32 += n - split;
             }
             ClassLists &cl = c->lists[X][Y];
-            STCHK(upload_list(c->screen_pool, cl.all64, b64, lo64, hi64));
-            STCHK(upload_list(c->screen_pool, cl.mix64, bm64, lom64, him64));
-            STCHK(upload_list(c->screen_pool, cl.mix32, bm32, lom32, him32));
+            STCHK(upload_list(c->screen_pool, cl.all64, b64, lo64, hi64, c->segt[X][Y][0],
+                              &cl.segcap[0]));
+            STCHK(upload_list(c->screen_pool, cl.mix64, bm64, lom64, him64, c->segt[X][Y][0],
+                              &cl.segcap[1]));
+            STCHK(upload_list(c->screen_pool, cl.mix32, bm32, lom32, him32, c->segt[X][Y][1],
+                              &cl.segcap[2]));
             cl.host[0] = HostList{b64, lo64, hi64};
             cl.host[1] = HostList{bm64, lom64, him64};
             cl.host[2] = HostList{bm32, lom32, him32};
@@ -1189,17 +1223,17 @@ extern "C" fsim_status fsim_schwarz_screen(fsim_ctx *c, double tau, double tau32
                 // cut again for every build, at most as many as the full list's
                 d.nseg = 0;
                 d.seg_rec = d.seg_t0 = d.seg_nt = nullptr;
-                cl.dseg[k].assign(3 * (size_t)full[k]->nseg, 0);
+                cl.dseg[k].assign(3 * (size_t)cl.segcap[k], 0);
                 cl.dnq[k] = 0;
                 cl.dstart[k].assign(d.nbra + 1, 0);
                 cl.dhi[k] = cl.host[k].lo;
                 if (d.nbra == 0) continue;
                 HIPCHK(c->screen_pool.alloc(&d.tile_start, (size_t)d.nbra + 1));
                 HIPCHK(c->screen_pool.alloc(&d.ket_hi, (size_t)d.nbra));
-                if (full[k]->nseg > 0) {
-                    HIPCHK(c->screen_pool.alloc(&d.seg_rec, (size_t)full[k]->nseg));
-                    HIPCHK(c->screen_pool.alloc(&d.seg_t0, (size_t)full[k]->nseg));
-                    HIPCHK(c->screen_pool.alloc(&d.seg_nt, (size_t)full[k]->nseg));
+                if (cl.segcap[k] > 0) {
+                    HIPCHK(c->screen_pool.alloc(&d.seg_rec, (size_t)cl.segcap[k]));
+                    HIPCHK(c->screen_pool.alloc(&d.seg_t0, (size_t)cl.segcap[k]));
+                    HIPCHK(c->screen_pool.alloc(&d.seg_nt, (size_t)cl.segcap[k]));
                 }
             }
             S.quartets_kept += cl.all64.nquartet;
@@ -1759,17 +1793,14 @@ static fsim_status delta_lists(fsim_ctx *c, double thr, hipStream_t s, int64_t *
                 d.ntile = h.bra.empty() ? 0 : st.back();
                 d.nquartet = nq;
                 cl.dnq[li] = nq;
-                // segments over the new tile ranges (never more than the full list's)
+                // segments over the new tile ranges, at the class's segment size
+                // (never more than the capacity, cut at the smallest size over
+                // the full ranges)
                 const size_t cap = cl.dseg[li].size() / 3;
                 int *srec = cl.dseg[li].data(), *st0 = srec + cap, *snt = st0 + cap;
-                size_t ns = 0;
-                for (size_t r = 0; r < h.bra.size() && cap > 0; ++r)
-                    for (int t = st[r]; t < st[r + 1]; t += SEG_TILES) {
-                        srec[ns] = (int)r;
-                        st0[ns] = t;
-                        snt[ns] = std::min(SEG_TILES, st[r + 1] - t);
-                        ++ns;
-                    }
+                const size_t ns = cap > 0 ? cut_segments(st, c->segt[X][Y][li == 2 ? 1 : 0],
+                                                         srec, st0, snt)
+                                          : 0;
                 d.nseg = (int)ns;
                 if (!h.bra.empty()) {
                     HIPCHK(hipMemcpyAsync(d.tile_start, st.data(), sizeof(int) * st.size(),
@@ -1887,6 +1918,35 @@ extern "C" fsim_status fsim_get_class_profile(fsim_ctx *c, fsim_class_profile *o
     return FSIM_OK;
 }
 
+// Cut every full tile list's segments again at its class's segment size
+// (after a tuning change); the device arrays hold segments of the smallest
+// size, so they always fit.  Synchronous copies: not for graph capture.
+static fsim_status set_segments(fsim_ctx *c) {
+    if (!c->screened) return FSIM_OK;
+    for (int X = 0; X < NPCLASS; ++X)
+        for (int Y = 0; Y <= X; ++Y) {
+            ClassLists &cl = c->lists[X][Y];
+            TileList *tls[3] = {&cl.all64, &cl.mix64, &cl.mix32};
+            for (int k = 0; k < 3; ++k) {
+                TileList &tl = *tls[k];
+                const size_t cap = (size_t)cl.segcap[k];
+                if (tl.nbra == 0 || cap == 0) continue;
+                const std::vector<int> st = tile_starts(cl.host[k].lo, cl.host[k].hi);
+                std::vector<int> h(3 * cap);
+                tl.nseg = (int)cut_segments(st, c->segt[X][Y][k == 2 ? 1 : 0], h.data(),
+                                            h.data() + cap, h.data() + 2 * cap);
+                HIPCHK(hipMemcpy(tl.seg_rec, h.data(), sizeof(int) * tl.nseg,
+                                 hipMemcpyHostToDevice));
+                HIPCHK(hipMemcpy(tl.seg_t0, h.data() + cap, sizeof(int) * tl.nseg,
+                                 hipMemcpyHostToDevice));
+                HIPCHK(hipMemcpy(tl.seg_nt, h.data() + 2 * cap, sizeof(int) * tl.nseg,
+                                 hipMemcpyHostToDevice));
+            }
+        }
+    drop_graphs(c);
+    return FSIM_OK;
+}
+
 extern "C" fsim_status fsim_set_tuning(fsim_ctx *c, const fsim_tuning *t, int32_t n) {
     if (!c || (n > 0 && !t)) return fail(FSIM_EINVAL, "NULL argument");
     for (int32_t k = 0; k < n; ++k) {
@@ -1899,13 +1959,20 @@ extern "C" fsim_status fsim_set_tuning(fsim_ctx *c, const fsim_tuning *t, int32_
         if (r.waves_per_block != 1 && r.waves_per_block != 2 && r.waves_per_block != 4 &&
             r.waves_per_block != 8)
             return fail(FSIM_EINVAL, "waves_per_block must be 1, 2, 4 or 8");
+        if (r.seg_tiles != 0 && !valid_seg(r.seg_tiles))
+            return fail(FSIM_EINVAL, "seg_tiles must be 0 or a power of 2 in 16..512");
     }
+    bool seg_changed = false;
     for (int32_t k = 0; k < n; ++k) {
         const fsim_tuning &r = t[k];
         c->variant[r.bra_class][r.ket_class][r.fp32] = r.variant;
         c->wpb[r.bra_class][r.ket_class][r.fp32] = r.waves_per_block;
         c->tuned_ms[r.bra_class][r.ket_class][r.fp32] = r.ms;
+        const int seg = r.seg_tiles ? r.seg_tiles : SEG_TILES;
+        seg_changed |= c->segt[r.bra_class][r.ket_class][r.fp32] != seg;
+        c->segt[r.bra_class][r.ket_class][r.fp32] = seg;
     }
+    if (seg_changed) STCHK(set_segments(c));
     drop_graphs(c);
     return FSIM_OK;
 }
@@ -1957,6 +2024,7 @@ extern "C" fsim_status fsim_get_tuning(fsim_ctx *c, fsim_tuning *out, int32_t ca
                     r.fp32 = f;
                     r.variant = c->variant[X][Y][f];
                     r.waves_per_block = c->wpb[X][Y][f];
+                    r.seg_tiles = c->segt[X][Y][f];
                     r.kbra = c->screened ? c->kept[X].kmax : c->all[X].kmax;
                     r.kket = c->screened ? c->kept[Y].kmax : c->all[Y].kmax;
                     r.ms = c->tuned_ms[X][Y][f];
@@ -2045,6 +2113,49 @@ extern "C" fsim_status fsim_autotune(fsim_ctx *c, const double *D, fsim_precisio
                 c->wpb[X][Y][f] = bw[X][Y][f];
                 if (best[X][Y][f] < 1e299) c->tuned_ms[X][Y][f] = best[X][Y][f];
             }
+    // segment size of the classes that chose segment mode: every class at
+    // its chosen variant, one build per size
+    if (st == FSIM_OK && c->krow_lds) {
+        const int sizes[4] = {32, 64, 128, 256};
+        double sbest[NPCLASS][NPCLASS][2];
+        int sz[NPCLASS][NPCLASS][2];
+        for (int X = 0; X < NPCLASS; ++X)
+            for (int Y = 0; Y < NPCLASS; ++Y)
+                for (int f = 0; f < 2; ++f) {
+                    sbest[X][Y][f] = 1e300;
+                    sz[X][Y][f] = SEG_TILES;
+                }
+        for (int k = 0; k < 4 && st == FSIM_OK; ++k) {
+            for (int X = 0; X < NPCLASS; ++X)
+                for (int Y = 0; Y < NPCLASS; ++Y)
+                    for (int f = 0; f < 2; ++f) c->segt[X][Y][f] = sizes[k];
+            st = set_segments(c);
+            if (st != FSIM_OK) break;
+            st = fock_build(c, D, c->F, nullptr, nullptr, nullptr, prec, s);
+            if (st != FSIM_OK) break;
+            if (verbose) {
+                double tot = 0.0;
+                for (const auto &r : c->prof) tot += r.ms;
+                std::fprintf(stderr, "[fsim_autotune] %s segments of %d tiles: %.1f ms\n",
+                             prec == FSIM_MIXED ? "mixed" : "fp64", sizes[k], tot);
+                std::fflush(stderr);
+            }
+            for (const auto &r : c->prof)
+                if (r.bra_class < NPCLASS && bw[r.bra_class][r.ket_class][r.fp32] == 8 &&
+                    r.ms < sbest[r.bra_class][r.ket_class][r.fp32]) {
+                    sbest[r.bra_class][r.ket_class][r.fp32] = r.ms;
+                    sz[r.bra_class][r.ket_class][r.fp32] = sizes[k];
+                }
+        }
+        for (int X = 0; X < NPCLASS; ++X)
+            for (int Y = 0; Y < NPCLASS; ++Y)
+                for (int f = 0; f < 2; ++f) {
+                    c->segt[X][Y][f] = sz[X][Y][f];
+                    if (sbest[X][Y][f] < 1e299) c->tuned_ms[X][Y][f] = sbest[X][Y][f];
+                }
+        const fsim_status s2 = set_segments(c);
+        if (st == FSIM_OK) st = s2;
+    }
     c->profiling = was;
     c->persistent = was_persistent;
     drop_graphs(c);

@@ -70,7 +70,8 @@ class _Tuning(ctypes.Structure):
     _fields_ = [("bra_class", ctypes.c_int32), ("ket_class", ctypes.c_int32),
                 ("fp32", ctypes.c_int32), ("variant", ctypes.c_int32),
                 ("waves_per_block", ctypes.c_int32), ("kbra", ctypes.c_int32),
-                ("kket", ctypes.c_int32), ("pad", ctypes.c_int32), ("ms", ctypes.c_double)]
+                ("kket", ctypes.c_int32), ("seg_tiles", ctypes.c_int32),
+                ("ms", ctypes.c_double)]
 
 
 PAIR_CLASS = ("ss", "ps", "pp", "ds", "dp", "dd", "sp*")   # "sp*": the persistent s/p launch
@@ -349,8 +350,8 @@ class Context:
         arr = (_Tuning * max(1, len(records)))()
         for k, r in enumerate(records):
             arr[k] = _Tuning(int(r["bra_class"]), int(r["ket_class"]), int(r["fp32"]),
-                             int(r["variant"]), int(r["waves_per_block"]), 0, 0, 0,
-                             float(r.get("ms", 0.0)))
+                             int(r["variant"]), int(r["waves_per_block"]), 0, 0,
+                             int(r.get("seg_tiles", 0)), float(r.get("ms", 0.0)))
         _check(lib().fsim_set_tuning(self.h, arr, len(records)))
 
     def set_all_variants(self, variant, waves_per_block=4):

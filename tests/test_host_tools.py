@@ -133,7 +133,7 @@ def test_autotune_cache_keys_and_apply():
     ctx = _FakeCtx(recs)
     assert autotune.apply(ctx, table) == 1
     assert ctx.set == [dict(bra_class=2, ket_class=1, fp32=0, variant=4, waves_per_block=2,
-                            ms=1.5)]
+                            seg_tiles=0, ms=1.5)]
 
 
 def test_committed_tuning_caches_are_well_formed():
@@ -143,6 +143,7 @@ def test_committed_tuning_caches_are_well_formed():
         for key, e in entries.items():
             assert key == autotune.cache_key(e)
             assert 0 <= e["variant"] < 7 and e["waves_per_block"] in (1, 2, 4, 8)
+            assert e.get("seg_tiles", 0) in (0, 16, 32, 64, 128, 256, 512)
 
 
 def test_cpu_baseline_samples_kept_quartets():

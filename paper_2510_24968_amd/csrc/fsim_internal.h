@@ -139,13 +139,13 @@ struct TileList {
     int *ket_hi = nullptr;       // [nbra]
     // segments (Fock builds with K' rows in LDS): segment s is the tiles
     // [seg_t0[s], seg_t0[s] + seg_nt[s]) of bra record seg_rec[s], at most
-    // SEG_TILES of them; nseg = 0: no segments
+    // the class's segment length of them; nseg = 0: no segments
     int nseg = 0;
     int *seg_rec = nullptr, *seg_t0 = nullptr, *seg_nt = nullptr;
 };
 
 constexpr int TILE = 64;        // kets per wave tile (one per lane)
-constexpr int SEG_TILES = 64;   // tiles per segment
+constexpr int SEG_TILES = 64;   // default tiles per segment (tuned per class)
 
 struct EriArgs {
     PairTable bra, ket;

@@ -290,7 +290,8 @@ fsim_status fsim_get_class_profile(fsim_ctx *ctx, fsim_class_profile *out, int32
  * 3).  waves_per_block is 1, 2 or 4 for launches over tiles, every K'
  * term a global atomic (variants 3 and 6 use one block shape), or 8 for the
  * segment mode of the lane variants 0, 1, 2, 4 and 5 (see
- * fsim_set_krow_lds: blocks of 8 waves, or 4 for kernels held to one wave
+ * fsim_set_krow_lds: blocks of 8 waves (12 for the ket-outer kernel of the
+ * s/p classes of total angular momentum 2), or 4 for kernels held to one wave
  * per SIMD, over segments of one bra's tiles with the bra's K' rows in LDS;
  * launches whose rows do not fit run over tiles with 4 waves per block).
  * The default is variant 1 in segment mode with 64 tiles per segment;

@@ -50,13 +50,37 @@ __device__ __forceinline__ void boys_large_t(double T, double e, double *F) {
     }
 }
 
-// F_0..F_L at T from a table staged for order L.  exp(-T), which both
-// branches need for L > 0, is evaluated once ahead of the branch: the lanes
-// of a wave often take both branches, which would otherwise run it twice.
-template <int L>
+// Optional exp column after the staged grid: exp(-T_k) at T_k = k * BOYS_DT
+// for k < BOYS_NE (T up to 100; beyond it exp(-T) < 4e-44 is taken as 0).
+// exp(-T) = exp(-T_k) * exp(T_k - T) with the second factor from its Taylor
+// series through d^8/8! (|T_k - T| <= 0.05, so the truncation is below 6e-18
+// relative): eight FMAs and one LDS read instead of the library exponential.
+constexpr int BOYS_NE = 1001;
+constexpr int BOYS_LDS_E = BOYS_LDS + BOYS_NE;
+
+__device__ inline void boys_stage_exp(double *lds) {
+    for (int i = threadIdx.x; i < BOYS_NE; i += blockDim.x) lds[BOYS_LDS + i] = exp(-i * BOYS_DT);
+}
+
+__device__ __forceinline__ double boys_exp_tab(double T, const double *etab) {
+    constexpr double TE = (BOYS_NE - 1) * BOYS_DT;
+    const double Tc = fmin(T, TE);
+    const int k = __double2int_rn(Tc * BOYS_INV_DT);
+    const double d = k * BOYS_DT - Tc;
+    double p = inv_factorial(8);
+#pragma unroll
+    for (int j = 7; j >= 0; --j) p = fma(p, d, inv_factorial(j));
+    return T <= TE ? etab[k] * p : 0.0;
+}
+
+// F_0..F_L at T from a table staged for order L (with the exp column when
+// ET).  exp(-T), which both branches need for L > 0, is evaluated once ahead
+// of the branch: the lanes of a wave often take both branches, which would
+// otherwise run it twice.
+template <int L, bool ET = false>
 __device__ __forceinline__ void boys_eval(double T, const double *tab, double *F) {
     double e = 0.0;
-    if constexpr (L > 0) e = exp(-T);
+    if constexpr (L > 0) e = ET ? boys_exp_tab(T, tab + BOYS_LDS) : exp(-T);
     if (T < BOYS_TMAX) {
         const int k = __double2int_rn(T * BOYS_INV_DT);
         const double d = k * BOYS_DT - T;

@@ -351,12 +351,16 @@ __global__ __launch_bounds__(SEG ? 64 * seg_waves(LA, LB, LC, LD, CA, CDC) : 256
     constexpr int NEB = n_entries(LA, LB), NEK = n_entries(LC, LD);
     constexpr int NCHA = (NA + CA - 1) / CA, NCHCD = (NCD + CDC - 1) / CDC;
     // Boys grid in LDS: FP64 for FP64 tiles, FP32 (5 terms, the Taylor step
-    // only) for FP32 tiles
+    // only) for FP32 tiles; FP64 tiles of s and p bras add the exp column
+    // (the d bras keep that LDS for their K' rows)
     constexpr bool F32 = std::is_same<T, float>::value;
-    __shared__ std::conditional_t<F32, float, double> tab[F32 ? BOYS_LDS32 : BOYS_LDS];
+    constexpr bool ET = !F32 && LA <= 1;
+    __shared__ std::conditional_t<F32, float, double>
+        tab[F32 ? BOYS_LDS32 : (ET ? BOYS_LDS_E : BOYS_LDS)];
     extern __shared__ __align__(16) unsigned char stage_lds[];
     if constexpr (F32) boys_stage32(tab, a.boys, L);
     else boys_stage(tab, a.boys, L);
+    if constexpr (ET) boys_stage_exp(tab);
     __syncthreads();
     const int lane = threadIdx.x & 63;
     const int wpb = blockDim.x >> 6;
@@ -515,7 +519,7 @@ __global__ __launch_bounds__(SEG ? 64 * seg_waves(LA, LB, LC, LD, CA, CDC) : 256
                         const double rs = rsqrt(p + q);
                         const double alpha = p * q * (rs * rs);
                         double F[L + 1];
-                        boys_eval<L>(alpha * (X * X + Y * Y + Z * Z), tab, F);
+                        boys_eval<L, ET>(alpha * (X * X + Y * Y + Z * Z), tab, F);
                         double m = rs;
 #pragma unroll
                         for (int n = 0; n <= L; ++n) {
@@ -627,10 +631,11 @@ __global__ __launch_bounds__(SEG ? 64 * seg_waves(LA, LB, LC, LD, CA, CDC) : 256
 // Boys-function providers of the ket-outer tile body: the class kernels
 // stage the grid pre-divided for their own order L (boys.h); the persistent
 // kernel stages raw F_n(T_k) for every order its classes need.
+template <bool ET>
 struct BoysStaged64 {
     const double *tab;
     template <int L>
-    __device__ __forceinline__ void eval(double T, double *F) const { boys_eval<L>(T, tab, F); }
+    __device__ __forceinline__ void eval(double T, double *F) const { boys_eval<L, ET>(T, tab, F); }
 };
 struct BoysStagedMixed {
     const float *tab;
@@ -844,25 +849,37 @@ __device__ __forceinline__ void ko_tile(const EriArgs &a, const int tile, const 
     });
 }
 
+// Blocks of the ket-outer kernel in segment mode: 12 waves for the s/p
+// classes of total angular momentum 2, whose ~150 registers allow three
+// waves per SIMD; 8 (two per SIMD) otherwise.
+__host__ __device__ constexpr int ko_seg_waves(int la, int lb, int lc, int ld) {
+    return la <= 1 && la + lb + lc + ld == 2 ? 12 : 8;
+}
+
 template <int LA, int LB, int LC, int LD, typename T, bool STORE, int CA, int CDC, bool SEG>
-__global__ __launch_bounds__(SEG ? 512 : 256) void k_eri_lane_ko(EriArgs a) {
+__global__ __launch_bounds__(SEG ? 64 * ko_seg_waves(LA, LB, LC, LD) : 256)
+void k_eri_lane_ko(EriArgs a) {
     constexpr int L = LA + LB + LC + LD;
     // Boys grid in LDS: FP64 for FP64 tiles, FP32 (5 terms, the Taylor step
-    // only) for FP32 tiles
+    // only) for FP32 tiles; FP64 tiles of s and p bras add the exp column
+    // (the d bras keep that LDS for their K' rows)
     constexpr bool F32 = std::is_same<T, float>::value;
-    __shared__ std::conditional_t<F32, float, double> tab[F32 ? BOYS_LDS32 : BOYS_LDS];
+    constexpr bool ET = !F32 && LA <= 1;
+    __shared__ std::conditional_t<F32, float, double>
+        tab[F32 ? BOYS_LDS32 : (ET ? BOYS_LDS_E : BOYS_LDS)];
     extern __shared__ __align__(16) unsigned char stage_lds[];
     if constexpr (F32) boys_stage32(tab, a.boys, L);
     else boys_stage(tab, a.boys, L);
+    if constexpr (ET) boys_stage_exp(tab);
     __syncthreads();
     const int wpb = blockDim.x >> 6;
     const int ntile = STORE ? a.st_ntile : a.tl.ntile;
     // every bra primitive of the tile is staged (the launch checks kmax fits)
     double *__restrict__ sp = (double *)(stage_lds + (size_t)(threadIdx.x >> 6) * a.stage_bytes);
-    using BP = std::conditional_t<F32, BoysStagedMixed, BoysStaged64>;
+    using BP = std::conditional_t<F32, BoysStagedMixed, BoysStaged64<ET>>;
     const BP bp{tab};
     if constexpr (SEG && !STORE) {
-        // segment mode: blocks of 8 waves share the bra's K' rows
+        // segment mode: the block's waves share the bra's K' rows
         double *__restrict__ krow = (double *)(stage_lds + (size_t)wpb * a.stage_bytes);
         const long long xoff = a.xcd_stride ? xcd_index() * a.xcd_stride : 0;
         run_segments<ncart(LA), ncart(LB)>(a, krow, xoff, [&](int t) __attribute__((always_inline)) {
@@ -1642,10 +1659,11 @@ void launch_ko(int ntile, int wpb, const EriArgs &a, hipStream_t s) {
             if constexpr (!STORE) {
                 if (wpb == 8) {
                     auto seg = k_eri_lane_ko<LA, LB, LC, LD, T, false, CA, CDC, true>;
+                    constexpr int W = ko_seg_waves(LA, LB, LC, LD);
                     int sblocks = 0;
                     size_t dyn = 0;
-                    if (segment_fit<LA, LB>((const void *)seg, 8, b, sblocks, dyn)) {
-                        hipLaunchKernelGGL(seg, dim3(sblocks), dim3(512), dyn, s, b);
+                    if (segment_fit<LA, LB>((const void *)seg, W, b, sblocks, dyn)) {
+                        hipLaunchKernelGGL(seg, dim3(sblocks), dim3(64 * W), dyn, s, b);
                         return;
                     }
                 }

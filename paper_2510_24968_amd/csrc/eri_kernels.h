@@ -351,16 +351,12 @@ __global__ __launch_bounds__(SEG ? 64 * seg_waves(LA, LB, LC, LD, CA, CDC) : 256
     constexpr int NEB = n_entries(LA, LB), NEK = n_entries(LC, LD);
     constexpr int NCHA = (NA + CA - 1) / CA, NCHCD = (NCD + CDC - 1) / CDC;
     // Boys grid in LDS: FP64 for FP64 tiles, FP32 (5 terms, the Taylor step
-    // only) for FP32 tiles; FP64 tiles of s and p bras add the exp column
-    // (the d bras keep that LDS for their K' rows)
+    // only) for FP32 tiles
     constexpr bool F32 = std::is_same<T, float>::value;
-    constexpr bool ET = !F32 && LA <= 1;
-    __shared__ std::conditional_t<F32, float, double>
-        tab[F32 ? BOYS_LDS32 : (ET ? BOYS_LDS_E : BOYS_LDS)];
+    __shared__ std::conditional_t<F32, float, double> tab[F32 ? BOYS_LDS32 : BOYS_LDS];
     extern __shared__ __align__(16) unsigned char stage_lds[];
     if constexpr (F32) boys_stage32(tab, a.boys, L);
     else boys_stage(tab, a.boys, L);
-    if constexpr (ET) boys_stage_exp(tab);
     __syncthreads();
     const int lane = threadIdx.x & 63;
     const int wpb = blockDim.x >> 6;
@@ -519,7 +515,7 @@ __global__ __launch_bounds__(SEG ? 64 * seg_waves(LA, LB, LC, LD, CA, CDC) : 256
                         const double rs = rsqrt(p + q);
                         const double alpha = p * q * (rs * rs);
                         double F[L + 1];
-                        boys_eval<L, ET>(alpha * (X * X + Y * Y + Z * Z), tab, F);
+                        boys_eval<L>(alpha * (X * X + Y * Y + Z * Z), tab, F);
                         double m = rs;
 #pragma unroll
                         for (int n = 0; n <= L; ++n) {
@@ -744,6 +740,16 @@ __device__ __forceinline__ void ko_tile(const EriArgs &a, const int tile, const 
                 ek[e - EK0] = ev;
             }
             for (int i = 0; i < nbp; ++i) {
+                // bras with small Hermite boxes (ss, ps) read this
+                // primitive's box entries here, in one batch with its p and
+                // P, instead of one LDS round trip per pair of entries in
+                // the bra step below
+                constexpr bool EPRE = NEB <= 8;
+                T ebr[EPRE ? NEB : 1];
+                if constexpr (EPRE) {
+#pragma unroll
+                    for (int e = 0; e < NEB; ++e) ebr[e] = se[i * NEB + e];
+                }
                 const double p = sp[i * 4 + 0];
                 const double X = sp[i * 4 + 1] - Kx, Y = sp[i * 4 + 2] - Ky,
                              Z = sp[i * 4 + 3] - Kz;
@@ -818,7 +824,7 @@ __device__ __forceinline__ void ko_tile(const EriArgs &a, const int tile, const 
                             static_for<az + 1>([&](auto v_) {
                                 constexpr int v = decltype(v_)::value;
                                 constexpr int e = ao + (t * (ay + 1) + u) * (az + 1) + v;
-                                const T ebv = eb[e];
+                                const T ebv = EPRE ? ebr[EPRE ? e : 0] : eb[e];
                                 static_for<NCDc>([&](auto cdl_) {
                                     constexpr int cdl = decltype(cdl_)::value;
                                     out[abl][cdl] = fma(ebv, V[cdl][hidx(t, u, v)], out[abl][cdl]);
@@ -861,10 +867,11 @@ __global__ __launch_bounds__(SEG ? 64 * ko_seg_waves(LA, LB, LC, LD) : 256)
 void k_eri_lane_ko(EriArgs a) {
     constexpr int L = LA + LB + LC + LD;
     // Boys grid in LDS: FP64 for FP64 tiles, FP32 (5 terms, the Taylor step
-    // only) for FP32 tiles; FP64 tiles of s and p bras add the exp column
-    // (the d bras keep that LDS for their K' rows)
+    // only) for FP32 tiles. FP64 tiles of s and p bras in segment mode add
+    // the exp column (the d bras keep that LDS for their K' rows; launches
+    // over tiles measured slower with it).
     constexpr bool F32 = std::is_same<T, float>::value;
-    constexpr bool ET = !F32 && LA <= 1;
+    constexpr bool ET = !F32 && LA <= 1 && SEG;
     __shared__ std::conditional_t<F32, float, double>
         tab[F32 ? BOYS_LDS32 : (ET ? BOYS_LDS_E : BOYS_LDS)];
     extern __shared__ __align__(16) unsigned char stage_lds[];

@@ -283,8 +283,9 @@ fsim_status fsim_get_class_profile(fsim_ctx *ctx, fsim_class_profile *out, int32
  * one-wave-per-quartet kernel, variant 4 the one-lane-per-quartet kernel with
  * the primitive loops in ket-outer order (ss, ps, pp and ds bra pairs; other
  * classes run variant 1), variant 5 the one-lane-per-quartet kernel at a
- * budget of 192 live values for classes whose chunks do not fit 160 (others
- * run variant 2), variant 6 the one-wave-per-quartet kernel whose two
+ * budget of 192 live values for classes whose chunks do not fit 160 or that
+ * need fewer chunks at 192 ((ds|pp), (dp|pp), (dp|ds); others run
+ * variant 2), variant 6 the one-wave-per-quartet kernel whose two
  * Hermite contraction steps run as dense products on the matrix cores
  * (16x16x4 FP64 / FP32 MFMA; classes with a d bra pair, others run variant
  * 3).  waves_per_block is 1, 2 or 4 for launches over tiles, every K'

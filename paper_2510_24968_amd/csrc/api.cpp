@@ -2036,6 +2036,36 @@ extern "C" fsim_status fsim_get_tuning(fsim_ctx *c, fsim_tuning *out, int32_t ca
     return FSIM_OK;
 }
 
+// Chunk count of the one-lane-per-quartet kernel for a class at a budget of
+// live values (the kernels' rule: halve the ket pair range, then the bra
+// range, until the chunk's accumulators, Hermite intermediates and R fit),
+// and whether the budget is met within 24 chunks.
+static int lane_chunks(int X, int Y, int limit, bool *fits) {
+    const int la = pclass_l1(X), lb = pclass_l2(X), lc = pclass_l1(Y), ld = pclass_l2(Y);
+    const int na = ncart(la), ncd = ncart(lc) * ncart(ld);
+    auto live = [&](int ca, int cdc) {
+        return ca * ncart(lb) * cdc + nherm(la + lb) * cdc + nherm(la + lb + lc + ld);
+    };
+    int ca = na, cdc = ncd;
+    while (live(ca, cdc) > limit) {
+        if (cdc > 1) cdc = (cdc + 1) / 2;
+        else if (ca > 1) ca = (ca + 1) / 2;
+        else break;
+    }
+    const int n = ((na + ca - 1) / ca) * ((ncd + cdc - 1) / cdc);
+    *fits = live(ca, cdc) <= limit && n <= 24;
+    return n;
+}
+
+// Variant 5 is a kernel of its own (192 live values) for the classes whose
+// chunks do not fit 160 or that need fewer chunks at 192; elsewhere it runs
+// variant 2 and is not worth timing.
+static bool wide_distinct(int X, int Y) {
+    bool f160 = false, f192 = false;
+    const int n160 = lane_chunks(X, Y, 160, &f160), n192 = lane_chunks(X, Y, 192, &f192);
+    return !f160 || (f192 && n192 < n160);
+}
+
 extern "C" fsim_status fsim_autotune(fsim_ctx *c, const double *D, fsim_precision prec,
                                      void *stream) {
     if (!c || !D) return fail(FSIM_EINVAL, "NULL argument");
@@ -2069,8 +2099,8 @@ extern "C" fsim_status fsim_autotune(fsim_ctx *c, const double *D, fsim_precisio
                 continue;   // one wave per block, or segment mode
             if (w == 3 && !c->krow_lds) continue;
             // the wave kernel is only a candidate for the high angular-momentum
-            // classes (L >= 5) and the ket-outer kernel only for the ss, ps, pp
-            // and ds bras;
+            // classes (L >= 5), the ket-outer kernel only for the ss, ps, pp
+            // and ds bras, and variant 5 only where it is a kernel of its own;
             // elsewhere those classes keep a lane variant during that pass and
             // are not scored in it
             const bool wave = v == ERI_VARIANT_WAVE, ko = v == ERI_VARIANT_KO,
@@ -2082,7 +2112,7 @@ extern "C" fsim_status fsim_autotune(fsim_ctx *c, const double *D, fsim_precisio
                 for (int Y = 0; Y < NPCLASS; ++Y)
                     for (int f = 0; f < 2; ++f) {
                         const bool cand = (!wave || Ltot(X, Y) >= 5) && (!ko || X <= 3) &&
-                                          (!wide || Ltot(X, Y) >= 7) && (!mf || X >= 3);
+                                          (!wide || wide_distinct(X, Y)) && (!mf || X >= 3);
                         c->variant[X][Y][f] = cand ? v : ERI_DEFAULT_VARIANT;
                         c->wpb[X][Y][f] = wpbs[w];
                     }
@@ -2098,7 +2128,7 @@ extern "C" fsim_status fsim_autotune(fsim_ctx *c, const double *D, fsim_precisio
             for (const auto &r : c->prof)
                 if ((!wave || Ltot(r.bra_class, r.ket_class) >= 5) &&
                     (!ko || r.bra_class <= 3) &&
-                    (!wide || Ltot(r.bra_class, r.ket_class) >= 7) &&
+                    (!wide || wide_distinct(r.bra_class, r.ket_class)) &&
                     (!mf || r.bra_class >= 3) &&
                     r.ms < best[r.bra_class][r.ket_class][r.fp32]) {
                     best[r.bra_class][r.ket_class][r.fp32] = r.ms;

@@ -1697,9 +1697,15 @@ void launch_variant(int ntile, int variant, int wpb, const EriArgs &a, hipStream
         case 2: launch_budget<LA, LB, LC, LD, T, STORE, variant_budget(2)>(ntile, wpb, a, s); break;
         case VARIANT_KO: launch_ko<LA, LB, LC, LD, T, STORE>(ntile, wpb, a, s); break;
         case VARIANT_WIDE:
-            // only classes whose smallest chunk exceeds 160 live values get a
-            // 192-value lane kernel; every other class runs variant 2
-            if constexpr (!lane_fits<LA, LB, LC, LD, variant_budget(2)>())
+            // a 192-value lane kernel for the classes whose smallest chunk
+            // exceeds 160 live values, or that need fewer chunks at 192
+            // ((ds|pp), (dp|pp), (dp|ds): each chunk re-evaluates Boys and
+            // R, and these run at one wave per SIMD either way); every other
+            // class runs variant 2
+            if constexpr (!lane_fits<LA, LB, LC, LD, variant_budget(2)>() ||
+                          (lane_fits<LA, LB, LC, LD, variant_budget(VARIANT_WIDE)>() &&
+                           n_chunks(LA, LB, LC, LD, variant_budget(VARIANT_WIDE)) <
+                               n_chunks(LA, LB, LC, LD, variant_budget(2))))
                 launch_budget<LA, LB, LC, LD, T, STORE, variant_budget(VARIANT_WIDE)>(ntile, wpb, a, s);
             else
                 launch_budget<LA, LB, LC, LD, T, STORE, variant_budget(2)>(ntile, wpb, a, s);

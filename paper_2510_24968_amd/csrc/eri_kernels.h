@@ -857,13 +857,17 @@ __device__ __forceinline__ void ko_tile(const EriArgs &a, const int tile, const 
 
 // Blocks of the ket-outer kernel in segment mode: 12 waves for the s/p
 // classes of total angular momentum 2, whose ~150 registers allow three
-// waves per SIMD; 8 (two per SIMD) otherwise.
-__host__ __device__ constexpr int ko_seg_waves(int la, int lb, int lc, int ld) {
-    return la <= 1 && la + lb + lc + ld == 2 ? 12 : 8;
+// waves per SIMD; 4 (one per SIMD, AGPRs available) for FP64 (ds|pp),
+// which at two waves per SIMD spills to scratch; 8 (two per SIMD)
+// otherwise.
+__host__ __device__ constexpr int ko_seg_waves(int la, int lb, int lc, int ld, bool f64) {
+    return la <= 1 && la + lb + lc + ld == 2 ? 12
+                                             : (f64 && la == 2 && lc == 1 && ld == 1 ? 4 : 8);
 }
 
 template <int LA, int LB, int LC, int LD, typename T, bool STORE, int CA, int CDC, bool SEG>
-__global__ __launch_bounds__(SEG ? 64 * ko_seg_waves(LA, LB, LC, LD) : 256)
+__global__ __launch_bounds__(SEG ? 64 * ko_seg_waves(LA, LB, LC, LD, !std::is_same<T, float>::value)
+                                 : 256)
 void k_eri_lane_ko(EriArgs a) {
     constexpr int L = LA + LB + LC + LD;
     // Boys grid in LDS: FP64 for FP64 tiles, FP32 (5 terms, the Taylor step
@@ -1666,7 +1670,8 @@ void launch_ko(int ntile, int wpb, const EriArgs &a, hipStream_t s) {
             if constexpr (!STORE) {
                 if (wpb == 8) {
                     auto seg = k_eri_lane_ko<LA, LB, LC, LD, T, false, CA, CDC, true>;
-                    constexpr int W = ko_seg_waves(LA, LB, LC, LD);
+                    constexpr int W =
+                        ko_seg_waves(LA, LB, LC, LD, !std::is_same<T, float>::value);
                     int sblocks = 0;
                     size_t dyn = 0;
                     if (segment_fit<LA, LB>((const void *)seg, W, b, sblocks, dyn)) {
